@@ -1,0 +1,137 @@
+"""ORACLE — test infrastructure only.
+
+A plain, slow, obviously correct CPU reference for what the library computes:
+
+* :mod:`oracle.encode` — the BLCO encoding (Section 4) in numpy;
+* this module — fp64 sparse MTTKRP (Eq. (1), Figure 3) and the sparse CP fit
+  loss and its gradient, through the C file ``mttkrp_oracle.c``.
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may
+import it.  It shares no code with the library under ``paper_2201_12523_amd``
+and the library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import encode  # noqa: F401  (re-export)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build_lib(force: bool = True) -> str:
+    if force or not os.path.exists(_SO):
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared",
+                               os.path.join(_HERE, "mttkrp_oracle.c"), "-o", _SO, "-lm"])
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build_lib(force=False)
+        L = ctypes.CDLL(_SO)
+        p, i64 = ctypes.c_void_p, ctypes.c_int64
+        L.oracle_mttkrp.argtypes = [ctypes.c_int, p, i64, p, p, p, ctypes.c_int, ctypes.c_int, p, p]
+        L.oracle_mttkrp_rows.argtypes = [ctypes.c_int, p, i64, p, p, p, ctypes.c_int, ctypes.c_int,
+                                         i64, p, p, p]
+        L.oracle_cp_model.argtypes = [ctypes.c_int, i64, p, p, ctypes.c_int, p]
+        L.oracle_cp_loss.argtypes = [ctypes.c_int, i64, p, p, p, ctypes.c_int, p]
+        L.oracle_cp_loss.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _ptrs(arrs):
+    return (ctypes.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+
+
+def mttkrp(coords, vals, factors, mode, dims=None, with_scale=True):
+    """Mode-``mode`` MTTKRP in fp64: returns (M, S) with S = sum of |terms|.
+
+    coords: list of N integer arrays (0-based); vals: nnz values; factors: list
+    of N arrays I_m x R (factors[mode] is not read, only its shape if dims is None).
+    All inputs are converted exactly to fp64 / uint32.
+    """
+    N = len(coords)
+    if dims is None:
+        dims = [f.shape[0] for f in factors]
+    R = int(factors[0].shape[1]) if factors[0] is not None else int(
+        [f for f in factors if f is not None][0].shape[1])
+    cs = [_c(c, np.uint32) for c in coords]
+    fs = [_c(f, np.float64) if f is not None else np.zeros((1, R)) for f in factors]
+    v = _c(vals, np.float64)
+    d = _c(dims, np.uint64)
+    I = int(dims[mode])
+    M = np.empty((I, R), dtype=np.float64)
+    S = np.empty((I, R), dtype=np.float64) if with_scale else None
+    lib().oracle_mttkrp(N, d.ctypes.data, len(v), _ptrs(cs), v.ctypes.data, _ptrs(fs), R, mode,
+                        M.ctypes.data, S.ctypes.data if S is not None else None)
+    return M, S
+
+
+def mttkrp_rows(coords, vals, factors, mode, rows, dims):
+    """Rows ``rows`` (distinct) of the mode-``mode`` MTTKRP: (M_rows, S_rows)."""
+    N = len(coords)
+    R = int([f for f in factors if f is not None][0].shape[1])
+    cs = [_c(c, np.uint32) for c in coords]
+    fs = [_c(f, np.float64) if f is not None else np.zeros((1, R)) for f in factors]
+    v = _c(vals, np.float64)
+    d = _c(dims, np.uint64)
+    rw = _c(rows, np.uint32)
+    M = np.empty((len(rw), R), dtype=np.float64)
+    S = np.empty((len(rw), R), dtype=np.float64)
+    lib().oracle_mttkrp_rows(N, d.ctypes.data, len(v), _ptrs(cs), v.ctypes.data, _ptrs(fs), R,
+                             mode, len(rw), rw.ctypes.data, M.ctypes.data, S.ctypes.data)
+    return M, S
+
+
+def cp_model(coords, factors):
+    """xhat_k = sum_r prod_m A^(m)[i_m^k, r] at every non-zero (fp64)."""
+    N = len(coords)
+    R = int(factors[0].shape[1])
+    cs = [_c(c, np.uint32) for c in coords]
+    fs = [_c(f, np.float64) for f in factors]
+    out = np.empty(len(cs[0]), dtype=np.float64)
+    lib().oracle_cp_model(N, len(out), _ptrs(cs), _ptrs(fs), R, out.ctypes.data)
+    return out
+
+
+def cp_loss(coords, vals, factors):
+    """(f, e): f = 1/2 sum_k e_k^2 with e_k = x_k - xhat_k (fp64)."""
+    N = len(coords)
+    R = int(factors[0].shape[1])
+    cs = [_c(c, np.uint32) for c in coords]
+    fs = [_c(f, np.float64) for f in factors]
+    v = _c(vals, np.float64)
+    e = np.empty(len(v), dtype=np.float64)
+    f = lib().oracle_cp_loss(N, len(v), _ptrs(cs), v.ctypes.data, _ptrs(fs), R, e.ctypes.data)
+    return float(f), e
+
+
+def cp_grad(coords, vals, factors, dims=None):
+    """Gradient of the sparse CP fit loss: G^(n) = -MTTKRP_n(E), E the residual tensor.
+
+    The loss is 1/2 sum_k e_k^2 with e_k = x_k - xhat_k; d xhat_k / d A^(n)[i,r]
+    is prod_{m != n} A^(m)[i_m^k, r] when i_n^k = i, so the gradient is the
+    mode-n MTTKRP of the tensor holding -e_k at the non-zeros.  Returns
+    (f, e, [G^(n)], [S^(n)]) with S^(n) the sum of |terms| of each entry.
+    """
+    f, e = cp_loss(coords, vals, factors)
+    G, S = [], []
+    for n in range(len(coords)):
+        g, s = mttkrp(coords, -e, factors, n, dims=dims)
+        G.append(g)
+        S.append(s)
+    return f, e, G, S
