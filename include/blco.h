@@ -1,0 +1,190 @@
+/*
+ * blco.h — C ABI of a sparse MTTKRP library over the Blocked Linearized
+ * CoOrdinate (BLCO) format for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Nguyen et al., "Efficient, Out-of-Memory Sparse MTTKRP on Massively
+ * Parallel Architectures", ICS '22 (arXiv 2201.12523).
+ *
+ * Conventions shared by every call
+ *   - Modes are 0-based (the paper counts from 1).  Coordinates are 0-based.
+ *   - A tensor has N = nmodes modes, 1 <= N <= BLCO_MAX_MODES, mode lengths
+ *     1 <= I_n <= 2^32.
+ *   - A factor matrix A^(m) is a dense I_m x R row-major array (row i holds
+ *     R contiguous elements) in device memory, fp32 or bf16 (BLCO_F32 /
+ *     BLCO_BF16), owned by the caller.  `factors` is a host array of N device
+ *     pointers; factors[mode] is not read and may be NULL.
+ *   - Outputs are dense I_n x R row-major fp32 in device memory, owned by the
+ *     caller, and OVERWRITTEN (Algorithm 1 assigns M).  An output must not
+ *     overlap a factor.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *     enqueued on it and the call returns without waiting; pointers passed in
+ *     must stay valid until that work has run.  Every argument is checked
+ *     before any device work is enqueued: on an error return nothing has
+ *     been written.  Errors raised while the work runs surface at the
+ *     caller's next synchronisation.
+ *   - Every call returns BLCO_OK (0) or a negative status; blco_last_error()
+ *     gives a message for the calling thread's last failure.
+ *   - Floating-point outputs of the MTTKRP calls depend on the order in which
+ *     atomic additions land, so they are not bitwise reproducible; keys,
+ *     blocks and every integer result are.
+ *   - Calls on one tensor may run concurrently only when they are in-memory
+ *     MTTKRP calls; blco_mttkrp_stream and blco_sampled_loss use buffers held
+ *     by the tensor and must not overlap another call on the same tensor.
+ */
+#ifndef BLCO_H
+#define BLCO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BLCO_MAX_MODES 8
+
+/* status codes */
+#define BLCO_OK 0
+#define BLCO_EINVAL (-1)       /* bad argument: null pointer, mode or rank out of range, ... */
+#define BLCO_ENOMEM (-2)       /* host or device allocation failed, or a budget is too small */
+#define BLCO_EDEVICE (-3)      /* a HIP call failed; the message holds hipGetErrorString */
+#define BLCO_ERANGE (-4)       /* a coordinate is >= its mode length */
+#define BLCO_EUNSUPPORTED (-5) /* N outside 1..8, a mode longer than 2^32, or a block key over 64 bits */
+
+/* factor storage */
+#define BLCO_F32 0
+#define BLCO_BF16 1
+
+/* where blco_build places the non-zeros */
+#define BLCO_PLACE_DEVICE 0 /* device memory: in-memory MTTKRP */
+#define BLCO_PLACE_PINNED 1 /* pinned host memory: streamed by blco_mttkrp_stream */
+#define BLCO_PLACE_HOST 2   /* pageable host memory only; no GPU call is made (inspection) */
+
+typedef struct blco_tensor blco_tensor;
+
+typedef struct {
+  int key_bits;          /* target integer width of a key, 1..64 (default 64), Section 4.2 */
+  int64_t max_block_nnz; /* cap on the non-zeros of a block, >= 1 (default 2^27), Section 4.2 */
+  int placement;         /* BLCO_PLACE_* (default BLCO_PLACE_DEVICE) */
+} blco_build_opts;
+
+typedef struct {
+  int nmodes;
+  int64_t nnz;
+  int total_bits;            /* T = sum of b_n */
+  int key_bits;              /* K = min(T, key_bits option): bits kept in a key */
+  int block_bits;            /* T - K: uppermost bits that form the block key */
+  int bits[BLCO_MAX_MODES];  /* b_n = ceil(log2 I_n) */
+  int kept[BLCO_MAX_MODES];  /* w_n: bits of mode n kept in the key */
+  int shift[BLCO_MAX_MODES]; /* s_n: position of mode n's field in the key */
+  int high[BLCO_MAX_MODES];  /* h_n: bits of mode n moved into the block key */
+  uint64_t dims[BLCO_MAX_MODES];
+  int64_t nblocks;           /* blocks after splitting to max_block_nnz */
+  int64_t nruns;             /* distinct block keys */
+  int placement;
+  size_t device_bytes;       /* device memory held by the tensor itself */
+  size_t host_bytes;         /* host memory held by the tensor */
+  size_t stream_peak_bytes;  /* last blco_mttkrp_stream call: factors + out + staging + tables */
+  int64_t stream_chunks;     /* last blco_mttkrp_stream call: chunks transferred */
+  int64_t stream_chunk_nnz;  /* last blco_mttkrp_stream call: non-zeros per staging buffer */
+} blco_info_t;
+
+/*
+ * Build a BLCO tensor from a COO tensor (Section 4; Figure 6).
+ *   nmodes, dims[nmodes]: the shape.  nnz >= 0 non-zeros.
+ *   coords[nmodes]: host arrays of nnz 0-based indices; values: host, nnz.
+ *   opts: NULL for the defaults.
+ * Steps: ALTO linearization of every coordinate (Section 4.1), a stable sort
+ * along the encoding line, re-encoding into per-mode bit fields decoded by
+ * shift and mask (Figure 6b), blocks on the uppermost T - K bits, split to
+ * at most max_block_nnz non-zeros (Section 4.2).  The inputs are copied: the
+ * caller may free them on return.  Duplicate coordinates are kept (their
+ * terms add up).  On success *out owns every buffer; release it with
+ * blco_free.  Errors: EINVAL, ERANGE, EUNSUPPORTED, ENOMEM, EDEVICE.
+ * This call is synchronous.
+ */
+int blco_build(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_t* const* coords,
+               const float* values, const blco_build_opts* opts, blco_tensor** out);
+
+/*
+ * Mode-`mode` MTTKRP (Eq. (1); Figure 3; Sections 5.1-5.2) of an in-memory
+ * tensor (placement DEVICE):
+ *   out[i, r] = sum over non-zeros k with i_mode = i of x_k * prod_{m != mode} A^(m)[i_m, r]
+ * factor_dtype: BLCO_F32 or BLCO_BF16 (products and sums are fp32 either way).
+ * rank R >= 1.  out: device, I_mode x R fp32, overwritten.
+ * Errors: EINVAL (null handle/pointer, mode, rank, dtype, placement).
+ */
+int blco_mttkrp(blco_tensor* t, int mode, const void* const* factors, int factor_dtype, int rank,
+                float* out, void* stream);
+
+/*
+ * As blco_mttkrp but accumulating: out += MTTKRP_mode (out is not cleared).
+ * For summing the MTTKRPs of several tensors that share factor matrices (for
+ * instance one tensor split over several BLCO copies).
+ */
+int blco_mttkrp_acc(blco_tensor* t, int mode, const void* const* factors, int factor_dtype,
+                    int rank, float* out, void* stream);
+
+/*
+ * As blco_mttkrp with the tensor's values replaced by `values` (device, nnz
+ * fp32, in the tensor's BLCO order, e.g. the residual written by
+ * blco_sampled_loss) and the result scaled:
+ *   out = alpha * (scale ? *scale : 1) * MTTKRP_mode(values)
+ * scale: device pointer to one double, or NULL.  This is the gradient of the
+ * sparse CP fit loss when values are the residuals and alpha = -1.
+ */
+int blco_mttkrp_v(blco_tensor* t, int mode, const float* values, const void* const* factors,
+                  int factor_dtype, int rank, const double* scale, double alpha, float* out,
+                  void* stream);
+
+/*
+ * Out-of-memory MTTKRP (Section 4.2): the non-zeros stay in pinned host
+ * memory (placement PINNED) and are streamed through at least two device
+ * staging buffers reused in turn; the copy of one chunk overlaps the kernel of
+ * the previous one.  device_budget_bytes bounds factors + out + staging +
+ * tables; the staging size is what remains, split in two (capped at
+ * max_block_nnz non-zeros each).  Result as blco_mttkrp.  A DEVICE tensor is
+ * computed in memory (the budget must still cover factors, out and tensor).
+ * Errors: as blco_mttkrp, plus ENOMEM when the budget cannot hold two
+ * staging buffers of one 64-non-zero tile each.  The staging buffers
+ * are allocated on the first call and kept by the tensor.
+ */
+int blco_mttkrp_stream(blco_tensor* t, int mode, const void* const* factors, int factor_dtype,
+                       int rank, float* out, size_t device_budget_bytes, void* stream);
+
+/*
+ * Sparse CP fit loss at the non-zeros (model of Section 2.2):
+ *   xhat_k = sum_r prod_{m} A^(m)[i_m^k, r],  e_k = x_k - xhat_k,
+ *   *loss = 1/2 sum_k e_k^2
+ * residual: device, nnz fp32, written in the tensor's BLCO order (may be NULL).
+ * loss: device pointer to one double.  Products are fp32; the residual norm
+ * is accumulated in fp64 in a fixed order (deterministic).  Placement DEVICE.
+ */
+int blco_sampled_loss(blco_tensor* t, const void* const* factors, int factor_dtype, int rank,
+                      float* residual, double* loss, void* stream);
+
+/* dst[i] = bf16(src[i]), round to nearest even (NaN stays NaN); device arrays. */
+int blco_cast_bf16(const float* src, uint16_t* dst, int64_t n, void* stream);
+
+/* Layout and sizes of a tensor. */
+int blco_info(const blco_tensor* t, blco_info_t* info);
+
+/*
+ * Copy the BLCO arrays to host memory (any placement; synchronous):
+ * keys[nnz], values[nnz], block_ids[nblocks], block_starts[nblocks + 1].
+ * Any pointer may be NULL to skip that array.
+ */
+int blco_export(const blco_tensor* t, uint64_t* keys, float* values, uint64_t* block_ids,
+                int64_t* block_starts);
+
+/* Release a tensor (NULL is ignored).  Waits for the tensor's own streams. */
+void blco_free(blco_tensor* t);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* blco_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLCO_H */

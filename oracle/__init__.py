@@ -57,6 +57,17 @@ def _ptrs(arrs):
     return (ctypes.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
 
 
+def bf16_round(a):
+    """fp32 values rounded to bfloat16 (8 significand bits), round to nearest even, as fp32.
+
+    The rounding of factor storage to bf16 is not fixed by the paper (which
+    uses fp64); round-to-nearest-even is the reading taken.  NaN is not expected.
+    """
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).reshape(np.shape(a))
+
+
 def mttkrp(coords, vals, factors, mode, dims=None, with_scale=True):
     """Mode-``mode`` MTTKRP in fp64: returns (M, S) with S = sum of |terms|.
 

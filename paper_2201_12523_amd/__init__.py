@@ -1,0 +1,313 @@
+"""Python binding of the BLCO sparse MTTKRP library (``libblco.so``, C ABI in include/blco.h).
+
+Argument marshalling only: every step of the computation runs in the library's
+HIP kernels.  PyTorch provides device memory and streams.  ``torch`` is
+imported before the library is loaded so that the library binds to the HIP
+runtime torch already uses (one runtime per process).
+
+Method: Nguyen et al., "Efficient, Out-of-Memory Sparse MTTKRP on Massively
+Parallel Architectures", ICS '22 — the BLCO format (Section 4) and its MTTKRP
+(Section 5).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading libblco.so)
+
+__all__ = ["BLCOTensor", "build", "mttkrp", "mttkrp_acc", "mttkrp_v", "mttkrp_stream", "sampled_loss",
+           "cast_bf16", "CPLoss", "BLCOError", "lib", "library_path"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libblco.so")
+_lib = None
+
+MAX_MODES = 8
+F32, BF16 = 0, 1
+PLACEMENTS = {"device": 0, "pinned": 1, "host": 2}
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: "EUNSUPPORTED"}
+
+EXPORTED = ["blco_build", "blco_mttkrp", "blco_mttkrp_acc", "blco_mttkrp_v", "blco_mttkrp_stream",
+            "blco_sampled_loss", "blco_cast_bf16", "blco_info", "blco_export", "blco_free",
+            "blco_last_error"]
+
+
+class BLCOError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("key_bits", ctypes.c_int), ("max_block_nnz", ctypes.c_int64),
+                ("placement", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("nmodes", ctypes.c_int), ("nnz", ctypes.c_int64), ("total_bits", ctypes.c_int),
+                ("key_bits", ctypes.c_int), ("block_bits", ctypes.c_int),
+                ("bits", ctypes.c_int * MAX_MODES), ("kept", ctypes.c_int * MAX_MODES),
+                ("shift", ctypes.c_int * MAX_MODES), ("high", ctypes.c_int * MAX_MODES),
+                ("dims", ctypes.c_uint64 * MAX_MODES), ("nblocks", ctypes.c_int64),
+                ("nruns", ctypes.c_int64), ("placement", ctypes.c_int),
+                ("device_bytes", ctypes.c_size_t), ("host_bytes", ctypes.c_size_t),
+                ("stream_peak_bytes", ctypes.c_size_t), ("stream_chunks", ctypes.c_int64),
+                ("stream_chunk_nnz", ctypes.c_int64)]
+
+
+def library_path() -> str:
+    return _SO
+
+
+def lib():
+    """The loaded ``libblco.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise RuntimeError(f"{_SO} is missing: build it with `python -m paper_2201_12523_amd.build`")
+        L = ctypes.CDLL(_SO)
+        p, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        L.blco_build.argtypes = [i32, p, i64, p, p, p, ctypes.POINTER(p)]
+        L.blco_mttkrp.argtypes = [p, i32, p, i32, i32, p, p]
+        L.blco_mttkrp_acc.argtypes = [p, i32, p, i32, i32, p, p]
+        L.blco_mttkrp_v.argtypes = [p, i32, p, p, i32, i32, p, ctypes.c_double, p, p]
+        L.blco_mttkrp_stream.argtypes = [p, i32, p, i32, i32, p, ctypes.c_size_t, p]
+        L.blco_sampled_loss.argtypes = [p, p, i32, i32, p, p, p]
+        L.blco_cast_bf16.argtypes = [p, p, i64, p]
+        L.blco_info.argtypes = [p, ctypes.POINTER(_Info)]
+        L.blco_export.argtypes = [p, p, p, p, p]
+        L.blco_free.argtypes = [p]
+        L.blco_free.restype = None
+        L.blco_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("blco_free", "blco_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise BLCOError(rc, lib().blco_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class BLCOTensor:
+    """A BLCO tensor owned by the library (freed with the object)."""
+
+    def __init__(self, handle, dims):
+        self._h = ctypes.c_void_p(handle)
+        self.dims = tuple(int(d) for d in dims)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(lib().blco_info(self._h, ctypes.byref(inf)))
+        N = inf.nmodes
+        return dict(nmodes=N, nnz=inf.nnz, total_bits=inf.total_bits, key_bits=inf.key_bits,
+                    block_bits=inf.block_bits, bits=list(inf.bits[:N]), kept=list(inf.kept[:N]),
+                    shift=list(inf.shift[:N]), high=list(inf.high[:N]), dims=list(inf.dims[:N]),
+                    nblocks=inf.nblocks, nruns=inf.nruns, placement=inf.placement,
+                    device_bytes=inf.device_bytes, host_bytes=inf.host_bytes,
+                    stream_peak_bytes=inf.stream_peak_bytes, stream_chunks=inf.stream_chunks,
+                    stream_chunk_nnz=inf.stream_chunk_nnz)
+
+    @property
+    def nnz(self) -> int:
+        return self.info()["nnz"]
+
+    @property
+    def nmodes(self) -> int:
+        return len(self.dims)
+
+    def export(self):
+        """(keys uint64, values float32, block_ids uint64, block_starts int64) on the host."""
+        inf = self.info()
+        n, nb = inf["nnz"], inf["nblocks"]
+        keys = np.empty(n, dtype=np.uint64)
+        vals = np.empty(n, dtype=np.float32)
+        bids = np.empty(nb, dtype=np.uint64)
+        bst = np.empty(nb + 1, dtype=np.int64)
+        _check(lib().blco_export(self._h, keys.ctypes.data, vals.ctypes.data, bids.ctypes.data,
+                                 bst.ctypes.data))
+        return keys, vals, bids, bst
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().blco_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build(coords, values, dims, key_bits=64, max_block_nnz=1 << 27, placement="device"):
+    """Build a BLCO tensor from 0-based COO coordinates (list of N integer arrays) and values."""
+    N = len(dims)
+    cs = [np.ascontiguousarray(c, dtype=np.uint32) for c in coords]
+    if len(cs) != N:
+        raise ValueError("one coordinate array per mode")
+    v = np.ascontiguousarray(values, dtype=np.float32)
+    d = np.ascontiguousarray(dims, dtype=np.uint64)
+    arr = (ctypes.c_void_p * N)(*[c.ctypes.data for c in cs])
+    opts = _Opts(key_bits, max_block_nnz, PLACEMENTS[placement])
+    h = ctypes.c_void_p()
+    _check(lib().blco_build(N, d.ctypes.data, len(v), arr, v.ctypes.data, ctypes.byref(opts),
+                            ctypes.byref(h)))
+    return BLCOTensor(h.value, dims)
+
+
+def _factor_args(t, factors, mode_skip):
+    dt = None
+    R = None
+    ptrs = []
+    keep = []
+    for m, f in enumerate(factors):
+        if f is None or (mode_skip is not None and m == mode_skip and f is None):
+            ptrs.append(None)
+            continue
+        if not f.is_cuda or not f.is_contiguous() or f.dim() != 2:
+            raise ValueError(f"factor {m} must be a contiguous 2-D device tensor")
+        if f.shape[0] != t.dims[m]:
+            raise ValueError(f"factor {m} has {f.shape[0]} rows, mode length is {t.dims[m]}")
+        fd = {torch.float32: F32, torch.bfloat16: BF16}.get(f.dtype)
+        if fd is None:
+            raise ValueError("factors must be float32 or bfloat16")
+        if dt is None:
+            dt, R = fd, int(f.shape[1])
+        elif fd != dt or int(f.shape[1]) != R:
+            raise ValueError("all factors must share dtype and rank")
+        ptrs.append(f.data_ptr())
+        keep.append(f)
+    if R is None:
+        raise ValueError("no factor given")
+    return (ctypes.c_void_p * len(factors))(*ptrs), dt, R, keep
+
+
+def _out(t, mode, R, out, device):
+    if out is None:
+        out = torch.empty((t.dims[mode], R), dtype=torch.float32, device=device)
+    elif (out.dtype != torch.float32 or not out.is_contiguous() or
+          tuple(out.shape) != (t.dims[mode], R)):
+        raise ValueError("out must be a contiguous float32 tensor of shape (I_mode, R)")
+    return out
+
+
+def _device_of(factors):
+    for f in factors:
+        if f is not None:
+            return f.device
+    return torch.device("cuda")
+
+
+def mttkrp(t, mode, factors, out=None, stream=None):
+    """Mode-``mode`` MTTKRP of an in-memory BLCO tensor; returns out (I_mode x R, float32)."""
+    arr, dt, R, _keep = _factor_args(t, factors, mode)
+    out = _out(t, mode, R, out, _device_of(factors))
+    _check(lib().blco_mttkrp(t.handle, mode, arr, dt, R, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def mttkrp_acc(t, mode, factors, out, stream=None):
+    """out += mode-``mode`` MTTKRP (out is not cleared first)."""
+    arr, dt, R, _keep = _factor_args(t, factors, mode)
+    out = _out(t, mode, R, out, _device_of(factors))
+    _check(lib().blco_mttkrp_acc(t.handle, mode, arr, dt, R, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def mttkrp_v(t, mode, values, factors, out=None, scale=None, alpha=1.0, stream=None):
+    """MTTKRP with the values replaced (device float32, BLCO order), scaled by alpha*scale."""
+    arr, dt, R, _keep = _factor_args(t, factors, mode)
+    out = _out(t, mode, R, out, _device_of(factors))
+    if values.dtype != torch.float32 or not values.is_contiguous():
+        raise ValueError("values must be contiguous float32")
+    sp = None
+    if scale is not None:
+        if scale.dtype != torch.float64 or scale.numel() != 1:
+            raise ValueError("scale must be a one-element float64 device tensor")
+        sp = scale.data_ptr()
+    _check(lib().blco_mttkrp_v(t.handle, mode, values.data_ptr(), arr, dt, R, sp, float(alpha),
+                               out.data_ptr(), _stream(stream)))
+    return out
+
+
+def mttkrp_stream(t, mode, factors, out=None, device_budget=8_000_000_000, stream=None):
+    """MTTKRP of a tensor in pinned host memory, streamed under a device-memory budget."""
+    arr, dt, R, _keep = _factor_args(t, factors, mode)
+    out = _out(t, mode, R, out, _device_of(factors))
+    _check(lib().blco_mttkrp_stream(t.handle, mode, arr, dt, R, out.data_ptr(),
+                                    int(device_budget), _stream(stream)))
+    return out
+
+
+def sampled_loss(t, factors, residual=None, loss=None, stream=None):
+    """(loss, residual): 1/2 sum_k (x_k - xhat_k)^2 as a float64 device scalar, and e (BLCO order)."""
+    arr, dt, R, _keep = _factor_args(t, factors, None)
+    dev = _device_of(factors)
+    n = t.nnz
+    if residual is None:
+        residual = torch.empty(n, dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float64, device=dev)
+    _check(lib().blco_sampled_loss(t.handle, arr, dt, R, residual.data_ptr(), loss.data_ptr(),
+                                   _stream(stream)))
+    return loss, residual
+
+
+def cast_bf16(x, stream=None):
+    """Round-to-nearest-even bfloat16 copy of a float32 device tensor (library kernel)."""
+    if x.dtype != torch.float32 or not x.is_contiguous():
+        raise ValueError("x must be contiguous float32")
+    y = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
+    _check(lib().blco_cast_bf16(x.data_ptr(), y.data_ptr(), x.numel(), _stream(stream)))
+    return y
+
+
+class CPLoss(torch.autograd.Function):
+    """Sparse CP fit loss 1/2 sum_nnz (x - sum_r prod_m A^(m))^2 with a hand-written backward.
+
+    forward(t, storage, *A): A are fp32 factor masters (I_m x R); storage "fp32"
+    or "bf16" (round-to-nearest-even copies used by the kernels).  The loss is
+    a float64 device scalar.  backward: dL/dA^(n) = -g * MTTKRP_n(E), E the
+    residual tensor, one MTTKRP per mode.
+    """
+
+    @staticmethod
+    def forward(ctx, t, storage, *A):
+        if storage == "bf16":
+            F = [cast_bf16(a.contiguous()) for a in A]
+        elif storage == "fp32":
+            F = [a.contiguous() for a in A]
+        else:
+            raise ValueError("storage must be 'fp32' or 'bf16'")
+        loss, resid = sampled_loss(t, F)
+        ctx.t = t
+        ctx.F = F
+        ctx.save_for_backward(resid)
+        return loss
+
+    @staticmethod
+    def backward(ctx, g):
+        (resid,) = ctx.saved_tensors
+        g = g.detach().reshape(1)
+        if g.dtype != torch.float64:
+            raise ValueError("loss gradient must be float64")
+        g = g.contiguous()
+        grads = [mttkrp_v(ctx.t, n, resid, ctx.F, scale=g, alpha=-1.0)
+                 for n in range(len(ctx.F))]
+        return (None, None, *grads)

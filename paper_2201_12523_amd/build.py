@@ -1,0 +1,52 @@
+"""Compile the BLCO library for gfx950 into ``paper_2201_12523_amd/libblco.so``.
+
+Host builder (``csrc/blco_host.cpp``) with g++, device runtime and kernels
+(``csrc/blco_device.hip``) with hipcc, linked with hipcc.  Run as
+``python -m paper_2201_12523_amd.build``.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "libblco.so")
+BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
+
+ARCH = "gfx950"
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIP_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    "-munsafe-fp-atomics",
+    # keep the compiler from forming packed fp32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+
+def _run(cmd):
+    t = time.time()
+    subprocess.check_call(cmd)
+    return time.time() - t
+
+
+def build(verbose: bool = True) -> str:
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    host_o = os.path.join(BUILD_DIR, "blco_host.o")
+    dev_o = os.path.join(BUILD_DIR, "blco_device.o")
+    t1 = _run(["g++", "-std=c++17", "-O3", "-fPIC", "-Wall", "-c",
+               os.path.join(CSRC, "blco_host.cpp"), "-o", host_o])
+    t2 = _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "blco_device.hip"), "-o", dev_o])
+    tmp = OUT + ".tmp"
+    t3 = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, dev_o, "-o", tmp,
+               "-lpthread"])
+    os.replace(tmp, OUT)
+    if verbose:
+        print(f"built {OUT} (host {t1:.1f}s, device {t2:.1f}s, link {t3:.1f}s)", file=sys.stderr)
+    return OUT
+
+
+if __name__ == "__main__":
+    build()

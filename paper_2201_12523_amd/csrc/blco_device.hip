@@ -1,0 +1,850 @@
+// Device runtime and gfx950 kernels of the BLCO sparse MTTKRP library.
+//
+// Method: Nguyen et al., "Efficient, Out-of-Memory Sparse MTTKRP on Massively
+// Parallel Architectures", ICS '22.  The MTTKRP kernel follows the
+// processing / computing split of Section 5.1 (Figure 7) with the
+// register-based conflict resolution of Section 5.2, re-designed for wave64:
+//   processing: each lane of a wave loads one (key, value) pair (coalesced),
+//     decodes every coordinate by shift and mask (Figure 6b), and the wave
+//     sorts its 64 non-zeros by target index with a bitonic network of
+//     cross-lane exchanges, so equal targets become contiguous segments whose
+//     ends form a 64-bit mask;
+//   computing: lanes are reassigned along the rank, one group of LPN lanes
+//     per non-zero; a group walks its run of sorted non-zeros, gathers the
+//     factor rows of the other modes, accumulates the scaled Hadamard product
+//     in a register while the target is unchanged and issues one atomic add
+//     per (segment, rank) at each segment end.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "blco_internal.h"
+#include "blco_kernels.h"
+
+using namespace blco;
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return set_error(BLCO_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+// ====================================================================== device code
+
+template <typename FT>
+__device__ __forceinline__ float ld_factor(const void* A, size_t i);
+
+template <>
+__device__ __forceinline__ float ld_factor<float>(const void* A, size_t i) {
+  return static_cast<const float*>(A)[i];
+}
+
+template <>
+__device__ __forceinline__ float ld_factor<uint16_t>(const void* A, size_t i) {
+  return __uint_as_float((uint32_t)static_cast<const uint16_t*>(A)[i] << 16);
+}
+
+// Coordinates of one non-zero: kept bits by shift and mask, the rest from
+// the block key of the run that holds it (Figure 6b).
+template <int N>
+__device__ __forceinline__ void decode(const KParams& p, uint64_t key, int64_t gidx,
+                                       uint32_t (&c)[N]) {
+  uint32_t base[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) base[m] = 0;
+  if (p.multi) {
+    int run = p.tile_run[gidx >> 6];
+    while (gidx >= p.run_start[run + 1]) ++run;
+#pragma unroll
+    for (int m = 0; m < N; ++m) base[m] = p.run_base[(size_t)run * N + m];
+  }
+#pragma unroll
+  for (int m = 0; m < N; ++m) c[m] = ((uint32_t)(key >> p.shift[m]) & p.mask[m]) | base[m];
+}
+
+// Ascending bitonic sort of one 32-bit value per lane across the wave.
+__device__ __forceinline__ uint32_t wave_sort32(uint32_t v, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      uint32_t o = (uint32_t)__shfl_xor((int)v, stride);
+      bool asc = (lane & size) == 0;
+      bool lower = (lane & stride) == 0;
+      uint32_t mn = min(v, o), mx = max(v, o);
+      v = (asc == lower) ? mn : mx;
+    }
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t v, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, stride);
+      uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), stride);
+      uint64_t o = ((uint64_t)hi << 32) | lo;
+      bool asc = (lane & size) == 0;
+      bool lower = (lane & stride) == 0;
+      uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
+      v = (asc == lower) ? mn : mx;
+    }
+  }
+  return v;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float term_scale(const KParams& p) {
+  return p.scale_dev ? (float)((double)p.scale * p.scale_dev[0]) : p.scale;
+}
+
+// Zero-fill of an output (a kernel rather than a memset so the call can be captured).
+__global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * 256;
+  if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+    float4* q = reinterpret_cast<float4*>(p);
+    int64_t n4 = n >> 2;
+    for (int64_t j = i; j < n4; j += stride) q[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t j = (n4 << 2) + i; j < n; j += stride) p[j] = 0.f;
+  } else {
+    for (int64_t j = i; j < n; j += stride) p[j] = 0.f;
+  }
+}
+
+// Reference-shaped kernel: one thread per (non-zero, rank), one atomic each.
+// Kept as the ablation point for the conflict resolution of the tile kernel.
+template <typename FT, int N>
+__global__ __launch_bounds__(256) void k_mttkrp_naive(KParams p) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t k = gid / p.R;
+  const int r = (int)(gid - k * p.R);
+  if (k >= p.n) return;
+  uint32_t c[N];
+  decode<N>(p, p.keys[k], p.base + k, c);
+  float v = p.vals[k] * term_scale(p);
+  uint32_t tgt = 0;
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    if (m == p.mode) {
+      tgt = c[m];
+    } else {
+      v *= ld_factor<FT>(p.A[m], (size_t)c[m] * p.R + r);
+    }
+  }
+  unsafeAtomicAdd(p.out + (size_t)tgt * p.R + r, v);
+}
+
+// BLCO MTTKRP, register-based conflict resolution (Sections 5.1-5.2).
+// One wave per tile of 64 consecutive non-zeros; LPN lanes per non-zero in the
+// computing phase, LPN non-zeros walked by each group.
+template <int LPN, typename FT, int N>
+__global__ __launch_bounds__(kBlock) void k_mttkrp_tile(KParams p) {
+  constexpr int G = 64 / LPN;    // groups per wave
+  constexpr int PPG = 64 / G;    // sorted positions per group
+  constexpr int NF = N + 1;      // coordinates + value
+  constexpr int U = PPG < 8 ? PPG : 8;
+  __shared__ uint32_t s[kWaves][64][NF];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t tile = (int64_t)blockIdx.x * kWaves + wv;
+  if (tile * 64 >= p.n) return;
+  const int64_t k = tile * 64 + lane;
+  const int nvalid = (int)min((int64_t)64, p.n - tile * 64);
+  const bool valid = lane < nvalid;
+
+  // processing phase: load, decode, sort by target, stage in sorted order
+  uint32_t c[N];
+  float x = 0.f;
+  if (valid) {
+    uint64_t key = p.keys[k];
+    x = p.vals[k];
+    decode<N>(p, key, p.base + k, c);
+  } else {
+#pragma unroll
+    for (int m = 0; m < N; ++m) c[m] = 0;
+  }
+  uint32_t tgt = 0;
+#pragma unroll
+  for (int m = 0; m < N; ++m)
+    if (m == p.mode) tgt = c[m];
+  int src;
+  uint32_t stgt;
+  if (!p.wide) {
+    uint32_t v = valid ? ((tgt << 6) | (uint32_t)lane) : 0xFFFFFFFFu;
+    v = wave_sort32(v, lane);
+    src = (int)(v & 63);
+    stgt = v >> 6;
+  } else {
+    uint64_t v = valid ? (((uint64_t)tgt << 6) | (uint64_t)lane) : ~0ULL;
+    v = wave_sort64(v, lane);
+    src = (int)(v & 63);
+    stgt = (uint32_t)(v >> 6);
+  }
+#pragma unroll
+  for (int m = 0; m < N; ++m) s[wv][lane][m] = (uint32_t)__shfl((int)c[m], src);
+  s[wv][lane][N] = (uint32_t)__shfl((int)__float_as_uint(x), src);
+  const uint32_t nxt = (uint32_t)__shfl((int)stgt, (lane + 1) & 63);
+  const bool end = (lane == nvalid - 1) || (lane < nvalid - 1 && nxt != stgt);
+  const uint64_t endm = __ballot(end);
+  wave_sync_lds();
+
+  // computing phase: rank-wise accumulate, flush at segment ends
+  const int g = lane / LPN;
+  const int rl = lane % LPN;
+  const float scale = term_scale(p);
+  const int R = p.R;
+  for (int r0 = 0; r0 < R; r0 += LPN) {
+    const int r = r0 + rl;
+    const bool ract = r < R;
+    const int rr = ract ? r : 0;
+    float acc = 0.f;
+    for (int q0 = 0; q0 < PPG; q0 += U) {
+      float pr[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t* e = s[wv][g * PPG + q0 + u];
+        float v = __uint_as_float(e[N]);
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+          if (m != p.mode) v *= ld_factor<FT>(p.A[m], (size_t)e[m] * R + rr);
+        pr[u] = v;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int pidx = g * PPG + q0 + u;
+        acc += pr[u];
+        if (((endm >> pidx) & 1) || (q0 + u == PPG - 1)) {
+          if (ract && pidx < nvalid) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m)
+              if (m == p.mode) t = s[wv][pidx][m];
+            unsafeAtomicAdd(p.out + (size_t)t * R + r, acc * scale);
+          }
+          acc = 0.f;
+        }
+      }
+    }
+  }
+}
+
+// Sampled reconstruction at the non-zeros, residual and fp64 partial sums of
+// the squared residual (CP model, Section 2.2).  One wave per tile; in the
+// computing phase a group of LPN lanes spans the rank of one non-zero.
+template <int LPN, typename FT, int N>
+__global__ __launch_bounds__(kBlock) void k_loss_tile(KParams p) {
+  constexpr int G = 64 / LPN;
+  constexpr int PPG = 64 / G;
+  constexpr int NF = N + 1;
+  constexpr int U = PPG < 4 ? PPG : 4;
+  __shared__ uint32_t s[kWaves][64][NF];
+  __shared__ float s_e[kWaves][64];
+  __shared__ double s_part[kWaves];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t tile = (int64_t)blockIdx.x * kWaves + wv;
+  const int64_t k = tile * 64 + lane;
+  const bool valid = k < p.n;
+  uint32_t c[N];
+  float x = 0.f;
+  if (valid) {
+    uint64_t key = p.keys[k];
+    x = p.vals[k];
+    decode<N>(p, key, p.base + k, c);
+  } else {
+#pragma unroll
+    for (int m = 0; m < N; ++m) c[m] = 0;
+  }
+#pragma unroll
+  for (int m = 0; m < N; ++m) s[wv][lane][m] = c[m];
+  s[wv][lane][N] = __float_as_uint(x);
+  wave_sync_lds();
+  const int g = lane / LPN;
+  const int rl = lane % LPN;
+  const int R = p.R;
+  for (int q0 = 0; q0 < PPG; q0 += U) {
+    float part[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t* e = s[wv][g * PPG + q0 + u];
+      float acc = 0.f;
+      for (int r = rl; r < R; r += LPN) {
+        float v = 1.f;
+#pragma unroll
+        for (int m = 0; m < N; ++m) v *= ld_factor<FT>(p.A[m], (size_t)e[m] * R + r);
+        acc += v;
+      }
+      part[u] = acc;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int off = LPN / 2; off > 0; off >>= 1) part[u] += __shfl_xor(part[u], off);
+      const int pidx = g * PPG + q0 + u;
+      if (rl == 0) s_e[wv][pidx] = __uint_as_float(s[wv][pidx][N]) - part[u];
+    }
+  }
+  wave_sync_lds();
+  const float e = s_e[wv][lane];
+  if (valid && p.out) p.out[k] = e;
+  double e2 = valid ? (double)e * (double)e : 0.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off);
+  if (lane == 0) s_part[wv] = e2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) t += s_part[w];
+    p.partials[blockIdx.x] = t;
+  }
+}
+
+// loss = 1/2 * sum of the partials, in a fixed order (one workgroup).
+__global__ __launch_bounds__(1024) void k_reduce_loss(const double* __restrict__ part, int64_t n,
+                                                      double* __restrict__ loss) {
+  __shared__ double sh[1024];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) a += part[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[0] = 0.5 * sh[0];
+}
+
+// fp32 -> bf16, round to nearest even; NaN stays a (quiet) NaN.
+__global__ __launch_bounds__(256) void k_cast_bf16(const float* __restrict__ src,
+                                                   uint16_t* __restrict__ dst, int64_t n) {
+  int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    uint32_t u = __float_as_uint(src[i]);
+    uint16_t b;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+      b = (uint16_t)((u >> 16) | 0x40u);
+    } else {
+      u += 0x7fffu + ((u >> 16) & 1u);
+      b = (uint16_t)(u >> 16);
+    }
+    dst[i] = b;
+  }
+}
+
+// ====================================================================== dispatch
+
+typedef void (*KernelFn)(KParams);
+
+template <int LPN, typename FT>
+static KernelFn pick_tile(int N) {
+  switch (N) {
+    case 1: return k_mttkrp_tile<LPN, FT, 1>;
+    case 2: return k_mttkrp_tile<LPN, FT, 2>;
+    case 3: return k_mttkrp_tile<LPN, FT, 3>;
+    case 4: return k_mttkrp_tile<LPN, FT, 4>;
+    case 5: return k_mttkrp_tile<LPN, FT, 5>;
+    case 6: return k_mttkrp_tile<LPN, FT, 6>;
+    case 7: return k_mttkrp_tile<LPN, FT, 7>;
+    default: return k_mttkrp_tile<LPN, FT, 8>;
+  }
+}
+
+template <int LPN, typename FT>
+static KernelFn pick_loss(int N) {
+  switch (N) {
+    case 1: return k_loss_tile<LPN, FT, 1>;
+    case 2: return k_loss_tile<LPN, FT, 2>;
+    case 3: return k_loss_tile<LPN, FT, 3>;
+    case 4: return k_loss_tile<LPN, FT, 4>;
+    case 5: return k_loss_tile<LPN, FT, 5>;
+    case 6: return k_loss_tile<LPN, FT, 6>;
+    case 7: return k_loss_tile<LPN, FT, 7>;
+    default: return k_loss_tile<LPN, FT, 8>;
+  }
+}
+
+template <typename FT>
+static KernelFn pick_naive(int N) {
+  switch (N) {
+    case 1: return k_mttkrp_naive<FT, 1>;
+    case 2: return k_mttkrp_naive<FT, 2>;
+    case 3: return k_mttkrp_naive<FT, 3>;
+    case 4: return k_mttkrp_naive<FT, 4>;
+    case 5: return k_mttkrp_naive<FT, 5>;
+    case 6: return k_mttkrp_naive<FT, 6>;
+    case 7: return k_mttkrp_naive<FT, 7>;
+    default: return k_mttkrp_naive<FT, 8>;
+  }
+}
+
+// lanes per non-zero in the computing phase: the rank rounded up to 16, 32 or 64
+static int lanes_per_nnz(int R) { return R <= 16 ? 16 : (R <= 32 ? 32 : 64); }
+
+static KernelFn select_tile(int N, int R, int fdt) {
+  int lpn = lanes_per_nnz(R);
+  if (fdt == BLCO_F32) {
+    if (lpn == 16) return pick_tile<16, float>(N);
+    if (lpn == 32) return pick_tile<32, float>(N);
+    return pick_tile<64, float>(N);
+  }
+  if (lpn == 16) return pick_tile<16, uint16_t>(N);
+  if (lpn == 32) return pick_tile<32, uint16_t>(N);
+  return pick_tile<64, uint16_t>(N);
+}
+
+static KernelFn select_loss(int N, int R, int fdt) {
+  int lpn = lanes_per_nnz(R);
+  if (fdt == BLCO_F32) {
+    if (lpn == 16) return pick_loss<16, float>(N);
+    if (lpn == 32) return pick_loss<32, float>(N);
+    return pick_loss<64, float>(N);
+  }
+  if (lpn == 16) return pick_loss<16, uint16_t>(N);
+  if (lpn == 32) return pick_loss<32, uint16_t>(N);
+  return pick_loss<64, uint16_t>(N);
+}
+
+// kernel variant: 0 = tile (default), 1 = one thread per (non-zero, rank)
+static int g_variant = -1;
+static int kernel_variant() {
+  if (g_variant < 0) {
+    const char* e = getenv("BLCO_KERNEL");
+    g_variant = (e && strcmp(e, "naive") == 0) ? 1 : 0;
+  }
+  return g_variant;
+}
+
+// ====================================================================== host runtime
+
+static void fill_params(const blco_tensor* t, KParams* p) {
+  memset(p, 0, sizeof(*p));
+  const Layout& L = t->lay;
+  for (int m = 0; m < L.N; ++m) {
+    p->shift[m] = L.w[m] ? (uint32_t)L.s[m] : 0u;
+    p->mask[m] = L.w[m] >= 32 ? 0xFFFFFFFFu : ((1u << L.w[m]) - 1u);
+  }
+  p->run_start = t->d_run_start;
+  p->run_base = t->d_run_base;
+  p->tile_run = t->d_tile_run;
+  p->multi = (t->run_start.size() > 2) ? 1 : 0;
+  if (t->run_start.size() == 2) {
+    for (int m = 0; m < L.N; ++m)
+      if (t->run_base[m]) p->multi = 1;
+  }
+  p->scale = 1.0f;
+}
+
+static int fill_zero(float* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return BLCO_OK;
+  int64_t blocks = std::min<int64_t>((n / 4 + 255) / 256 + 1, 8192);
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, out, n);
+  HIPCHK(hipGetLastError());
+  return BLCO_OK;
+}
+
+static int check_factor_args(const blco_tensor* t, int mode, const void* const* factors, int fdt,
+                             int rank, const float* out, bool need_mode_factor) {
+  if (!t) return set_error(BLCO_EINVAL, "tensor is NULL");
+  const int N = t->lay.N;
+  if (mode < 0 || mode >= N) return set_error(BLCO_EINVAL, "mode %d outside 0..%d", mode, N - 1);
+  if (rank < 1) return set_error(BLCO_EINVAL, "rank %d < 1", rank);
+  if (fdt != BLCO_F32 && fdt != BLCO_BF16) return set_error(BLCO_EINVAL, "factor dtype %d", fdt);
+  if (!factors) return set_error(BLCO_EINVAL, "factors is NULL");
+  for (int m = 0; m < N; ++m)
+    if ((m != mode || need_mode_factor) && !factors[m] && t->nnz > 0)
+      return set_error(BLCO_EINVAL, "factors[%d] is NULL", m);
+  if (!out) return set_error(BLCO_EINVAL, "out is NULL");
+  return BLCO_OK;
+}
+
+// Launch the MTTKRP kernel over [lo, lo + n) of the tensor given by keys/vals.
+static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float* vals,
+                         int64_t lo, int64_t n, int mode, const void* const* factors, int fdt,
+                         int rank, float scale, const double* scale_dev, float* out,
+                         hipStream_t s) {
+  if (n <= 0) return BLCO_OK;
+  KParams p;
+  fill_params(t, &p);
+  p.keys = keys;
+  p.vals = vals;
+  p.base = lo;
+  p.n = n;
+  for (int m = 0; m < t->lay.N; ++m) p.A[m] = factors[m];
+  p.out = out;
+  p.R = rank;
+  p.mode = mode;
+  p.wide = t->lay.dims[mode] > ((1ULL << 26) - 1) ? 1 : 0;
+  p.scale = scale;
+  p.scale_dev = scale_dev;
+  if (kernel_variant() == 1) {
+    int64_t threads = n * (int64_t)rank;
+    int64_t blocks = (threads + 255) / 256;
+    KernelFn f = (fdt == BLCO_F32) ? pick_naive<float>(t->lay.N) : pick_naive<uint16_t>(t->lay.N);
+    hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, s, p);
+  } else {
+    int64_t tiles = (n + 63) / 64;
+    int64_t blocks = (tiles + kWaves - 1) / kWaves;
+    KernelFn f = select_tile(t->lay.N, rank, fdt);
+    hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(kBlock), 0, s, p);
+  }
+  HIPCHK(hipGetLastError());
+  return BLCO_OK;
+}
+
+static void* pinned_alloc(size_t n) {
+  void* p = nullptr;
+  if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) return nullptr;
+  return p;
+}
+static void pinned_free(void* p) { (void)hipHostFree(p); }
+
+static size_t factor_elem_bytes(int fdt) { return fdt == BLCO_BF16 ? 2 : 4; }
+
+template <class T>
+static int upload(T** dst, const T* src, size_t count, size_t* acc) {
+  size_t bytes = sizeof(T) * std::max<size_t>(count, 1);
+  HIPCHK(hipMalloc((void**)dst, bytes));
+  if (count) HIPCHK(hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice));
+  *acc += bytes;
+  return BLCO_OK;
+}
+
+static void release_device(blco_tensor* t) {
+  StreamState& st = t->st;
+  if (st.copy_stream) {
+    (void)hipStreamSynchronize((hipStream_t)st.copy_stream);
+    for (int i = 0; i < 2; ++i) {
+      if (st.ev_free[i]) (void)hipEventSynchronize((hipEvent_t)st.ev_free[i]);
+    }
+  }
+  for (int i = 0; i < 2; ++i) {
+    if (st.d_keys[i]) (void)hipFree(st.d_keys[i]);
+    if (st.d_vals[i]) (void)hipFree(st.d_vals[i]);
+    if (st.ev_ready[i]) (void)hipEventDestroy((hipEvent_t)st.ev_ready[i]);
+    if (st.ev_free[i]) (void)hipEventDestroy((hipEvent_t)st.ev_free[i]);
+  }
+  if (st.copy_stream) (void)hipStreamDestroy((hipStream_t)st.copy_stream);
+  st = StreamState();
+  if (t->d_keys) (void)hipFree(t->d_keys);
+  if (t->d_vals) (void)hipFree(t->d_vals);
+  if (t->d_run_start) (void)hipFree(t->d_run_start);
+  if (t->d_run_base) (void)hipFree(t->d_run_base);
+  if (t->d_tile_run) (void)hipFree(t->d_tile_run);
+  if (t->d_partials) (void)hipFree(t->d_partials);
+  t->d_keys = nullptr;
+  t->d_vals = nullptr;
+  t->d_run_start = nullptr;
+  t->d_run_base = nullptr;
+  t->d_tile_run = nullptr;
+  t->d_partials = nullptr;
+}
+
+// ====================================================================== C ABI
+
+extern "C" int blco_build(int nmodes, const uint64_t* dims, int64_t nnz,
+                          const uint32_t* const* coords, const float* values,
+                          const blco_build_opts* opts, blco_tensor** out) {
+  clear_error();
+  if (!out) return set_error(BLCO_EINVAL, "out is NULL");
+  *out = nullptr;
+  int key_bits = 64;
+  int64_t cap = (int64_t)1 << 27;
+  int placement = BLCO_PLACE_DEVICE;
+  if (opts) {
+    key_bits = opts->key_bits;
+    cap = opts->max_block_nnz;
+    placement = opts->placement;
+  }
+  if (placement != BLCO_PLACE_DEVICE && placement != BLCO_PLACE_PINNED &&
+      placement != BLCO_PLACE_HOST)
+    return set_error(BLCO_EINVAL, "placement %d", placement);
+  blco_tensor* t = new (std::nothrow) blco_tensor();
+  if (!t) return set_error(BLCO_ENOMEM, "host allocation failed");
+  t->placement = placement;
+  HostAlloc ha = nullptr;
+  HostFree hf = nullptr;
+  if (placement == BLCO_PLACE_PINNED) {
+    ha = pinned_alloc;
+    hf = pinned_free;
+  }
+  int rc = host_build(nmodes, dims, nnz, coords, values, key_bits, cap, ha, hf, t);
+  if (rc) {
+    delete t;
+    return rc;
+  }
+  if (placement == BLCO_PLACE_HOST) {
+    *out = t;
+    return BLCO_OK;
+  }
+  auto fail = [&](int code) {
+    release_device(t);
+    free_host_arrays(t);
+    delete t;
+    return code;
+  };
+  if (hipGetDevice(&t->device) != hipSuccess) {
+    set_error(BLCO_EDEVICE, "hipGetDevice failed");
+    return fail(BLCO_EDEVICE);
+  }
+  size_t acc = 0;
+  if ((rc = upload(&t->d_run_start, t->run_start.data(), t->run_start.size(), &acc))) return fail(rc);
+  if ((rc = upload(&t->d_run_base, t->run_base.data(), t->run_base.size(), &acc))) return fail(rc);
+  if ((rc = upload(&t->d_tile_run, t->tile_run.data(), t->tile_run.size(), &acc))) return fail(rc);
+  if (placement == BLCO_PLACE_DEVICE) {
+    if ((rc = upload(&t->d_keys, t->h_keys, (size_t)nnz, &acc))) return fail(rc);
+    if ((rc = upload(&t->d_vals, t->h_vals, (size_t)nnz, &acc))) return fail(rc);
+    free_host_arrays(t);
+  }
+  t->device_bytes = acc;
+  *out = t;
+  return BLCO_OK;
+}
+
+extern "C" int blco_mttkrp_v(blco_tensor* t, int mode, const float* values,
+                             const void* const* factors, int factor_dtype, int rank,
+                             const double* scale, double alpha, float* out, void* stream) {
+  clear_error();
+  int rc = check_factor_args(t, mode, factors, factor_dtype, rank, out, false);
+  if (rc) return rc;
+  if (t->placement != BLCO_PLACE_DEVICE)
+    return set_error(BLCO_EINVAL, "in-memory MTTKRP needs a tensor placed on the device");
+  if (!values && t->nnz > 0) return set_error(BLCO_EINVAL, "values is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = fill_zero(out, (int64_t)t->lay.dims[mode] * rank, s))) return rc;
+  return launch_mttkrp(t, t->d_keys, values, 0, t->nnz, mode, factors, factor_dtype, rank,
+                       (float)alpha, scale, out, s);
+}
+
+extern "C" int blco_mttkrp(blco_tensor* t, int mode, const void* const* factors, int factor_dtype,
+                           int rank, float* out, void* stream) {
+  clear_error();
+  int rc = check_factor_args(t, mode, factors, factor_dtype, rank, out, false);
+  if (rc) return rc;
+  if (t->placement != BLCO_PLACE_DEVICE)
+    return set_error(BLCO_EINVAL, "in-memory MTTKRP needs a tensor placed on the device; "
+                                  "use blco_mttkrp_stream for a pinned tensor");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = fill_zero(out, (int64_t)t->lay.dims[mode] * rank, s))) return rc;
+  return launch_mttkrp(t, t->d_keys, t->d_vals, 0, t->nnz, mode, factors, factor_dtype, rank,
+                       1.0f, nullptr, out, s);
+}
+
+extern "C" int blco_mttkrp_acc(blco_tensor* t, int mode, const void* const* factors,
+                               int factor_dtype, int rank, float* out, void* stream) {
+  clear_error();
+  int rc = check_factor_args(t, mode, factors, factor_dtype, rank, out, false);
+  if (rc) return rc;
+  if (t->placement != BLCO_PLACE_DEVICE)
+    return set_error(BLCO_EINVAL, "in-memory MTTKRP needs a tensor placed on the device");
+  return launch_mttkrp(t, t->d_keys, t->d_vals, 0, t->nnz, mode, factors, factor_dtype, rank,
+                       1.0f, nullptr, out, (hipStream_t)stream);
+}
+
+extern "C" int blco_mttkrp_stream(blco_tensor* t, int mode, const void* const* factors,
+                                  int factor_dtype, int rank, float* out,
+                                  size_t device_budget_bytes, void* stream) {
+  clear_error();
+  int rc = check_factor_args(t, mode, factors, factor_dtype, rank, out, false);
+  if (rc) return rc;
+  const Layout& L = t->lay;
+  size_t fixed = (size_t)L.dims[mode] * rank * sizeof(float);
+  for (int m = 0; m < L.N; ++m)
+    if (m != mode) fixed += (size_t)L.dims[m] * rank * factor_elem_bytes(factor_dtype);
+  fixed += t->device_bytes;
+  if (t->placement == BLCO_PLACE_DEVICE) {
+    if (fixed > device_budget_bytes)
+      return set_error(BLCO_ENOMEM, "budget %zu below factors + out + tensor = %zu",
+                       device_budget_bytes, fixed);
+    t->stream_peak_bytes = fixed;
+    t->stream_chunks = 0;
+    return blco_mttkrp(t, mode, factors, factor_dtype, rank, out, stream);
+  }
+  if (t->placement != BLCO_PLACE_PINNED)
+    return set_error(BLCO_EINVAL, "streaming needs a tensor in pinned host memory");
+  const size_t per_nnz = sizeof(uint64_t) + sizeof(float);
+  if (device_budget_bytes < fixed + 2 * 64 * per_nnz)
+    return set_error(BLCO_ENOMEM, "budget %zu cannot hold factors + out + tables (%zu) and two "
+                                  "staging buffers", device_budget_bytes, fixed);
+  int64_t cap = (int64_t)((device_budget_bytes - fixed) / 2 / per_nnz);
+  int64_t blk_cap = ((t->max_block_nnz + 63) / 64) * 64;
+  cap = std::min(cap, blk_cap);
+  cap = std::min(cap, ((t->nnz + 63) / 64) * 64);
+  cap = (cap / 64) * 64;
+  if (cap < 64) cap = 64;
+  StreamState& st = t->st;
+  hipStream_t s = (hipStream_t)stream;
+  if (!st.copy_stream) {
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    st.copy_stream = cs;
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e1, e2;
+      HIPCHK(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
+      st.ev_ready[i] = e1;
+      st.ev_free[i] = e2;
+    }
+  }
+  if (st.cap_nnz != cap) {
+    // buffers of another size: wait until no kernel reads the old ones, then replace them
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(hipEventSynchronize((hipEvent_t)st.ev_free[i]));
+      if (st.d_keys[i]) HIPCHK(hipFree(st.d_keys[i]));
+      if (st.d_vals[i]) HIPCHK(hipFree(st.d_vals[i]));
+      st.d_keys[i] = nullptr;
+      st.d_vals[i] = nullptr;
+    }
+    st.cap_nnz = 0;
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(hipMalloc((void**)&st.d_keys[i], sizeof(uint64_t) * (size_t)cap));
+      HIPCHK(hipMalloc((void**)&st.d_vals[i], sizeof(float) * (size_t)cap));
+    }
+    st.cap_nnz = cap;
+  }
+  if ((rc = fill_zero(out, (int64_t)L.dims[mode] * rank, s))) return rc;
+  int64_t chunks = 0;
+  for (int64_t lo = 0; lo < t->nnz; lo += cap, ++chunks) {
+    const int b = (int)(chunks & 1);
+    const int64_t cnt = std::min(cap, t->nnz - lo);
+    hipStream_t cs = (hipStream_t)st.copy_stream;
+    HIPCHK(hipStreamWaitEvent(cs, (hipEvent_t)st.ev_free[b], 0));
+    HIPCHK(hipMemcpyAsync(st.d_keys[b], t->h_keys + lo, sizeof(uint64_t) * (size_t)cnt,
+                          hipMemcpyHostToDevice, cs));
+    HIPCHK(hipMemcpyAsync(st.d_vals[b], t->h_vals + lo, sizeof(float) * (size_t)cnt,
+                          hipMemcpyHostToDevice, cs));
+    HIPCHK(hipEventRecord((hipEvent_t)st.ev_ready[b], cs));
+    HIPCHK(hipStreamWaitEvent(s, (hipEvent_t)st.ev_ready[b], 0));
+    if ((rc = launch_mttkrp(t, st.d_keys[b], st.d_vals[b], lo, cnt, mode, factors, factor_dtype,
+                            rank, 1.0f, nullptr, out, s)))
+      return rc;
+    HIPCHK(hipEventRecord((hipEvent_t)st.ev_free[b], s));
+  }
+  t->stream_peak_bytes = fixed + 2 * (size_t)cap * per_nnz;
+  t->stream_chunks = chunks;
+  return BLCO_OK;
+}
+
+extern "C" int blco_sampled_loss(blco_tensor* t, const void* const* factors, int factor_dtype,
+                                 int rank, float* residual, double* loss, void* stream) {
+  clear_error();
+  if (!t) return set_error(BLCO_EINVAL, "tensor is NULL");
+  if (!loss) return set_error(BLCO_EINVAL, "loss is NULL");
+  if (rank < 1) return set_error(BLCO_EINVAL, "rank %d < 1", rank);
+  if (factor_dtype != BLCO_F32 && factor_dtype != BLCO_BF16)
+    return set_error(BLCO_EINVAL, "factor dtype %d", factor_dtype);
+  if (!factors) return set_error(BLCO_EINVAL, "factors is NULL");
+  for (int m = 0; m < t->lay.N; ++m)
+    if (!factors[m] && t->nnz > 0) return set_error(BLCO_EINVAL, "factors[%d] is NULL", m);
+  if (t->placement != BLCO_PLACE_DEVICE)
+    return set_error(BLCO_EINVAL, "the sampled loss needs a tensor placed on the device");
+  hipStream_t s = (hipStream_t)stream;
+  int64_t tiles = (t->nnz + 63) / 64;
+  int64_t blocks = std::max<int64_t>((tiles + kWaves - 1) / kWaves, 1);
+  if (t->partials_cap < blocks) {
+    if (t->d_partials) {
+      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipFree(t->d_partials));
+      t->d_partials = nullptr;
+      t->partials_cap = 0;
+    }
+    HIPCHK(hipMalloc((void**)&t->d_partials, sizeof(double) * (size_t)blocks));
+    t->partials_cap = blocks;
+  }
+  KParams p;
+  fill_params(t, &p);
+  p.keys = t->d_keys;
+  p.vals = t->d_vals;
+  p.base = 0;
+  p.n = t->nnz;
+  for (int m = 0; m < t->lay.N; ++m) p.A[m] = factors[m];
+  p.out = residual;
+  p.partials = t->d_partials;
+  p.R = rank;
+  p.mode = -1;
+  KernelFn f = select_loss(t->lay.N, rank, factor_dtype);
+  hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(kBlock), 0, s, p);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(1024), 0, s, (const double*)t->d_partials,
+                     blocks, loss);
+  HIPCHK(hipGetLastError());
+  return BLCO_OK;
+}
+
+extern "C" int blco_cast_bf16(const float* src, uint16_t* dst, int64_t n, void* stream) {
+  clear_error();
+  if (n < 0) return set_error(BLCO_EINVAL, "n < 0");
+  if (n == 0) return BLCO_OK;
+  if (!src || !dst) return set_error(BLCO_EINVAL, "src or dst is NULL");
+  int64_t blocks = std::min<int64_t>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_cast_bf16, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, src,
+                     dst, n);
+  HIPCHK(hipGetLastError());
+  return BLCO_OK;
+}
+
+extern "C" int blco_info(const blco_tensor* t, blco_info_t* info) {
+  clear_error();
+  if (!t || !info) return set_error(BLCO_EINVAL, "tensor or info is NULL");
+  memset(info, 0, sizeof(*info));
+  const Layout& L = t->lay;
+  info->nmodes = L.N;
+  info->nnz = t->nnz;
+  info->total_bits = L.T;
+  info->key_bits = L.K;
+  info->block_bits = L.S;
+  for (int m = 0; m < L.N; ++m) {
+    info->bits[m] = L.b[m];
+    info->kept[m] = L.w[m];
+    info->shift[m] = L.s[m];
+    info->high[m] = L.h[m];
+    info->dims[m] = L.dims[m];
+  }
+  info->nblocks = (int64_t)t->block_id.size();
+  info->nruns = (int64_t)t->run_start.size() - 1;
+  info->placement = t->placement;
+  info->device_bytes = t->device_bytes;
+  info->host_bytes = (t->h_keys ? (size_t)t->nnz * (sizeof(uint64_t) + sizeof(float)) : 0);
+  info->stream_peak_bytes = t->stream_peak_bytes;
+  info->stream_chunks = t->stream_chunks;
+  info->stream_chunk_nnz = t->st.cap_nnz;
+  return BLCO_OK;
+}
+
+extern "C" int blco_export(const blco_tensor* t, uint64_t* keys, float* values,
+                           uint64_t* block_ids, int64_t* block_starts) {
+  clear_error();
+  if (!t) return set_error(BLCO_EINVAL, "tensor is NULL");
+  const size_t n = (size_t)t->nnz;
+  if (keys && n) {
+    if (t->h_keys) memcpy(keys, t->h_keys, n * sizeof(uint64_t));
+    else HIPCHK(hipMemcpy(keys, t->d_keys, n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  }
+  if (values && n) {
+    if (t->h_vals) memcpy(values, t->h_vals, n * sizeof(float));
+    else HIPCHK(hipMemcpy(values, t->d_vals, n * sizeof(float), hipMemcpyDeviceToHost));
+  }
+  if (block_ids && !t->block_id.empty())
+    memcpy(block_ids, t->block_id.data(), t->block_id.size() * sizeof(uint64_t));
+  if (block_starts) memcpy(block_starts, t->block_start.data(), t->block_start.size() * sizeof(int64_t));
+  return BLCO_OK;
+}
+
+extern "C" void blco_free(blco_tensor* t) {
+  if (!t) return;
+  if (t->placement != BLCO_PLACE_HOST) release_device(t);
+  free_host_arrays(t);
+  delete t;
+}

@@ -1,0 +1,86 @@
+// Internal definitions shared by the host builder and the device runtime of
+// the BLCO library.  Not installed; the public interface is include/blco.h.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/blco.h"
+
+namespace blco {
+
+constexpr int kTile = 64;  // non-zeros per wave tile (one per lane of a wave64)
+
+// The bit map of a tensor (Sections 4.1-4.2).
+struct Layout {
+  int N = 0;
+  uint64_t dims[BLCO_MAX_MODES] = {};
+  int b[BLCO_MAX_MODES] = {};        // bits per mode
+  int pos[BLCO_MAX_MODES][32] = {};  // ALTO position of bit j of mode n
+  int T = 0, K = 0, S = 0;           // total bits, kept bits, block-key bits
+  int w[BLCO_MAX_MODES] = {};        // kept bits of mode n
+  int s[BLCO_MAX_MODES] = {};        // field shift of mode n in the key
+  int h[BLCO_MAX_MODES] = {};        // bits of mode n in the block key
+};
+
+// Device-side state used only by blco_mttkrp_stream (owned by the tensor).
+struct StreamState {
+  void* copy_stream = nullptr;     // hipStream_t, library-owned, default priority
+  void* ev_ready[2] = {nullptr, nullptr};
+  void* ev_free[2] = {nullptr, nullptr};
+  uint64_t* d_keys[2] = {nullptr, nullptr};
+  float* d_vals[2] = {nullptr, nullptr};
+  int64_t cap_nnz = 0;             // non-zeros per staging buffer
+};
+
+}  // namespace blco
+
+struct blco_tensor {
+  blco::Layout lay;
+  int64_t nnz = 0;
+  int placement = BLCO_PLACE_DEVICE;
+  int64_t max_block_nnz = 0;
+  // blocks after splitting (export / info), and runs of equal block key (kernels)
+  std::vector<uint64_t> block_id;
+  std::vector<int64_t> block_start;  // nblocks + 1
+  std::vector<int64_t> run_start;    // nruns + 1
+  std::vector<uint32_t> run_base;    // nruns * N: high bits of mode n of the run, already shifted by w_n
+  std::vector<int32_t> tile_run;     // per 64-non-zero tile: run holding its first non-zero
+  // host arrays (HOST: malloc, PINNED: hipHostMalloc; DEVICE: released after upload)
+  uint64_t* h_keys = nullptr;
+  float* h_vals = nullptr;
+  void (*host_free)(void*) = nullptr;
+  // device arrays
+  uint64_t* d_keys = nullptr;
+  float* d_vals = nullptr;
+  int64_t* d_run_start = nullptr;
+  uint32_t* d_run_base = nullptr;
+  int32_t* d_tile_run = nullptr;
+  double* d_partials = nullptr;  // sampled-loss partial sums (one per tile group)
+  int64_t partials_cap = 0;
+  size_t device_bytes = 0;
+  blco::StreamState st;
+  size_t stream_peak_bytes = 0;
+  int64_t stream_chunks = 0;
+  int device = -1;
+};
+
+namespace blco {
+
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+
+typedef void* (*HostAlloc)(size_t);
+typedef void (*HostFree)(void*);
+
+// Host half of blco_build: validates, linearizes, sorts, re-encodes, blocks.
+// Fills everything but the device arrays.  h_keys/h_vals come from `alloc`
+// and are released with `release` (NULL: malloc/free).
+int host_build(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_t* const* coords,
+               const float* values, int key_bits, int64_t max_block_nnz, HostAlloc alloc,
+               HostFree release, blco_tensor* t);
+
+void free_host_arrays(blco_tensor* t);
+
+}  // namespace blco

@@ -1,0 +1,36 @@
+// Device kernels of the BLCO library (gfx950, wave64).  Included by
+// blco_device.hip only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace blco {
+
+constexpr int kWaves = 4;             // waves per workgroup
+constexpr int kBlock = kWaves * 64;   // threads per workgroup
+
+// Everything a launch over one contiguous range of non-zeros needs.
+struct KParams {
+  const uint64_t* keys;   // keys[0] is global non-zero `base`
+  const float* vals;
+  int64_t base;           // global index of keys[0]; a multiple of 64
+  int64_t n;              // non-zeros in this launch
+  const int64_t* run_start;   // runs of equal block key (global indices)
+  const uint32_t* run_base;   // nruns x N: high bits of each mode, in place
+  const int32_t* tile_run;    // global tile -> run of its first non-zero
+  int multi;                  // more than one run (else every base is 0)
+  const void* A[8];           // factor matrices (A[mode] unused by MTTKRP)
+  float* out;                 // MTTKRP: I_mode x R; loss: residual (nnz)
+  double* partials;           // loss: one fp64 partial sum per workgroup
+  int R;
+  int mode;
+  uint32_t shift[8];
+  uint32_t mask[8];
+  int wide;                   // target index >= 2^26: sort 64-bit keys
+  float scale;                // host-side scale of every term
+  const double* scale_dev;    // optional device-side scale (one double)
+};
+
+}  // namespace blco

@@ -172,3 +172,15 @@ def test_synthetic_workload_small_against_brute_force_rows():
             ref += float(vals[k]) * A[1][coords[1][k]].astype(np.float64) * \
                 A[2][coords[2][k]].astype(np.float64)
         np.testing.assert_allclose(Mr[j], ref, rtol=1e-12, atol=1e-12)
+
+
+def test_bf16_round_pins():
+    # bf16 keeps 8 significand bits: 1 + 2^-8 is a tie between 1 and 1 + 2^-7 -> even (1);
+    # 1 + 3*2^-8 ties between 1 + 2^-7 and 1 + 2^-6 -> even (1 + 2^-6); exact values stay
+    x = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -7, -2.5, 0.0, 1 + 2.0 ** -9],
+                 dtype=np.float32)
+    assert oracle.bf16_round(x).tolist() == [1.0, 1 + 2.0 ** -6, 1 + 2.0 ** -7, -2.5, 0.0, 1.0]
+    r = np.random.default_rng(0).standard_normal(1000).astype(np.float32)
+    y = oracle.bf16_round(r)
+    assert np.all(np.abs(y - r) <= np.abs(r) * 2.0 ** -8)
+    assert np.all(y.view(np.uint32) & 0xFFFF == 0)
