@@ -182,7 +182,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{w.name}: {N}-mode {'x'.join(str(d) for d in w.dims)}, {nnz} distinct "
-                        f"non-zeros, per-mode {w.index_dist[0][0]}({w.index_dist[0][1]}) indices, "
+                        f"non-zeros, per-mode {'/'.join(map(str, w.index_dist[0]))} indices, "
                         f"U(0,1) values, rank {R} N(0,1) factors; all-mode MTTKRP from one BLCO copy",
             "nnz": nnz, "dims": list(w.dims), "rank": R, "modes": N,
             "key_bits": inf["total_bits"], "blocks": inf["nblocks"],
@@ -190,7 +190,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_mttkrp_tile<32, float, 3>",
+            "kernel": "k_mttkrp_win<32, float, 3>" if os.environ.get("BLCO_KERNEL", "win") == "win" else os.environ.get("BLCO_KERNEL"),
             "bytes_per_nnz": per_nnz,
             "avg_kernel_ms": avg_kernel_ms,
         },

@@ -240,6 +240,171 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tile(KParams p) {
   }
 }
 
+// Exchange of one value between lanes `stride` apart across a workgroup:
+// within a wave by a cross-lane permute, across waves through LDS.
+template <int STRIDE>
+__device__ __forceinline__ uint32_t xchg32(uint32_t v, int tid, uint32_t* lds) {
+  if constexpr (STRIDE < 64) {
+    return (uint32_t)__shfl_xor((int)v, STRIDE);
+  } else {
+    lds[tid] = v;
+    __syncthreads();
+    uint32_t o = lds[tid ^ STRIDE];
+    __syncthreads();
+    return o;
+  }
+}
+
+template <int STRIDE>
+__device__ __forceinline__ uint64_t xchg64(uint64_t v, int tid, uint64_t* lds) {
+  if constexpr (STRIDE < 64) {
+    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, STRIDE);
+    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), STRIDE);
+    return ((uint64_t)hi << 32) | lo;
+  } else {
+    lds[tid] = v;
+    __syncthreads();
+    uint64_t o = lds[tid ^ STRIDE];
+    __syncthreads();
+    return o;
+  }
+}
+
+template <typename K, int SIZE, int STRIDE>
+__device__ __forceinline__ K bitonic_step(K v, int tid, K* lds) {
+  K o;
+  if constexpr (sizeof(K) == 4) o = (K)xchg32<STRIDE>((uint32_t)v, tid, (uint32_t*)lds);
+  else o = (K)xchg64<STRIDE>((uint64_t)v, tid, (uint64_t*)lds);
+  const bool asc = (tid & SIZE) == 0;
+  const bool lower = (tid & STRIDE) == 0;
+  const K mn = v < o ? v : o;
+  const K mx = v < o ? o : v;
+  return (asc == lower) ? mn : mx;
+}
+
+template <typename K, int SIZE, int STRIDE>
+__device__ __forceinline__ K bitonic_merge(K v, int tid, K* lds) {
+  v = bitonic_step<K, SIZE, STRIDE>(v, tid, lds);
+  if constexpr (STRIDE > 1) v = bitonic_merge<K, SIZE, STRIDE / 2>(v, tid, lds);
+  return v;
+}
+
+// Ascending bitonic sort of one key per thread over a workgroup of WIN threads.
+template <typename K, int WIN, int SIZE = 2>
+__device__ __forceinline__ K block_sort(K v, int tid, K* lds) {
+  v = bitonic_merge<K, SIZE, SIZE / 2>(v, tid, lds);
+  if constexpr (SIZE < WIN) v = block_sort<K, WIN, SIZE * 2>(v, tid, lds);
+  return v;
+}
+
+constexpr int kWin = 1024;     // non-zeros per window (one per thread of the workgroup)
+constexpr int kWinBits = 10;
+
+// BLCO MTTKRP with register-based conflict resolution over a window of 1024
+// consecutive non-zeros per workgroup (Sections 5.1-5.2).  The processing
+// phase sorts the whole window by target index (a workgroup-wide bitonic
+// network: in-wave stages by cross-lane permutes, cross-wave stages through
+// LDS), so every target's terms form one segment; the computing phase walks
+// the sorted window with LPN lanes per non-zero and issues one atomic add
+// per (segment, rank).  On MI355X same-address atomics serialise (about
+// 32 ns each), so the wider window directly shortens the atomic chains of
+// frequent output rows.
+template <int LPN, typename FT, int N>
+__global__ __launch_bounds__(kWin) void k_mttkrp_win(KParams p) {
+  constexpr int G = kWin / LPN;   // groups of LPN lanes
+  constexpr int PPG = kWin / G;   // sorted positions per group (= LPN)
+  constexpr int U = PPG < 8 ? PPG : 8;
+  __shared__ uint32_t s_c[N][kWin];       // decoded coordinates by window position
+  __shared__ float s_x[kWin];             // values by window position
+  __shared__ uint64_t s_key[kWin];        // sorted (target, position) keys
+  __shared__ uint64_t s_end[kWin / 64];   // segment-end bits by sorted position
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  int64_t win = blockIdx.x;
+  if (p.xcd_remap) {
+    // consecutive windows to the same XCD (workgroups are dealt round robin over 8 XCDs)
+    const int64_t per = gridDim.x / 8;
+    if (win < per * 8) win = (win % 8) * per + win / 8;
+  }
+  const int64_t k0 = win * kWin;
+  if (k0 >= p.n) return;
+  const int nvalid = (int)min((int64_t)kWin, p.n - k0);
+  const bool valid = tid < nvalid;
+
+  // processing phase
+  uint32_t c[N];
+  float x = 0.f;
+  if (valid) {
+    const uint64_t key = p.keys[k0 + tid];
+    x = p.vals[k0 + tid];
+    decode<N>(p, key, p.base + k0 + tid, c);
+  } else {
+#pragma unroll
+    for (int m = 0; m < N; ++m) c[m] = 0;
+  }
+#pragma unroll
+  for (int m = 0; m < N; ++m) s_c[m][tid] = c[m];
+  s_x[tid] = x;
+  uint32_t tgt = 0;
+#pragma unroll
+  for (int m = 0; m < N; ++m)
+    if (m == p.mode) tgt = c[m];
+  uint64_t sk;
+  if (!p.wide) {
+    uint32_t v = valid ? ((tgt << kWinBits) | (uint32_t)tid) : 0xFFFFFFFFu;
+    v = block_sort<uint32_t, kWin>(v, tid, (uint32_t*)s_key);
+    sk = ((uint64_t)(v >> kWinBits) << kWinBits) | (v & (kWin - 1));
+  } else {
+    uint64_t v = valid ? (((uint64_t)tgt << kWinBits) | (uint64_t)tid) : ~0ULL;
+    sk = block_sort<uint64_t, kWin>(v, tid, s_key);
+  }
+  s_key[tid] = sk;
+  __syncthreads();
+  const bool end = (tid < nvalid) &&
+                   (tid == nvalid - 1 || (s_key[tid + 1] >> kWinBits) != (sk >> kWinBits));
+  const uint64_t em = __ballot(end);
+  if (lane == 0) s_end[tid >> 6] = em;
+  __syncthreads();
+
+  // computing phase
+  const int g = tid / LPN;
+  const int rl = tid % LPN;
+  const int p0 = g * PPG;
+  const uint64_t endw = s_end[p0 >> 6] >> (p0 & 63);
+  const float scale = term_scale(p);
+  const int R = p.R;
+  for (int r0 = 0; r0 < R; r0 += LPN) {
+    const int r = r0 + rl;
+    const bool ract = r < R;
+    const int rr = ract ? r : 0;
+    float acc = 0.f;
+    for (int q0 = 0; q0 < PPG; q0 += U) {
+      float pr[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int src = (int)(s_key[p0 + q0 + u] & (kWin - 1));
+        float v = s_x[src];
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+          if (m != p.mode) v *= ld_factor<FT>(p.A[m], (size_t)s_c[m][src] * R + rr);
+        pr[u] = v;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u;
+        acc += pr[u];
+        if (((endw >> q) & 1) || q == PPG - 1) {
+          if (ract && p0 + q < nvalid) {
+            const uint64_t t = s_key[p0 + q] >> kWinBits;
+            unsafeAtomicAdd(p.out + (size_t)t * R + r, acc * scale);
+          }
+          acc = 0.f;
+        }
+      }
+    }
+  }
+}
+
 // Sampled reconstruction at the non-zeros, residual and fp64 partial sums of
 // the squared residual (CP model, Section 2.2).  One wave per tile; in the
 // computing phase a group of LPN lanes spans the rank of one non-zero.
@@ -363,6 +528,20 @@ static KernelFn pick_tile(int N) {
 }
 
 template <int LPN, typename FT>
+static KernelFn pick_win(int N) {
+  switch (N) {
+    case 1: return k_mttkrp_win<LPN, FT, 1>;
+    case 2: return k_mttkrp_win<LPN, FT, 2>;
+    case 3: return k_mttkrp_win<LPN, FT, 3>;
+    case 4: return k_mttkrp_win<LPN, FT, 4>;
+    case 5: return k_mttkrp_win<LPN, FT, 5>;
+    case 6: return k_mttkrp_win<LPN, FT, 6>;
+    case 7: return k_mttkrp_win<LPN, FT, 7>;
+    default: return k_mttkrp_win<LPN, FT, 8>;
+  }
+}
+
+template <int LPN, typename FT>
 static KernelFn pick_loss(int N) {
   switch (N) {
     case 1: return k_loss_tile<LPN, FT, 1>;
@@ -405,6 +584,18 @@ static KernelFn select_tile(int N, int R, int fdt) {
   return pick_tile<64, uint16_t>(N);
 }
 
+static KernelFn select_win(int N, int R, int fdt) {
+  int lpn = lanes_per_nnz(R);
+  if (fdt == BLCO_F32) {
+    if (lpn == 16) return pick_win<16, float>(N);
+    if (lpn == 32) return pick_win<32, float>(N);
+    return pick_win<64, float>(N);
+  }
+  if (lpn == 16) return pick_win<16, uint16_t>(N);
+  if (lpn == 32) return pick_win<32, uint16_t>(N);
+  return pick_win<64, uint16_t>(N);
+}
+
 static KernelFn select_loss(int N, int R, int fdt) {
   int lpn = lanes_per_nnz(R);
   if (fdt == BLCO_F32) {
@@ -417,12 +608,23 @@ static KernelFn select_loss(int N, int R, int fdt) {
   return pick_loss<64, uint16_t>(N);
 }
 
-// kernel variant: 0 = tile (default), 1 = one thread per (non-zero, rank)
+// MTTKRP kernel variant, chosen once per process from BLCO_KERNEL:
+//   "win" (default): 1024-non-zero windows sorted per workgroup;
+//   "tile": 64-non-zero tiles sorted per wave;
+//   "naive": one thread and one atomic per (non-zero, rank).
+// BLCO_XCD_REMAP=1 gives consecutive windows to the same XCD (measured slower
+// on the Zipf workloads, so off by default).
+enum { kVarWin = 0, kVarTile = 1, kVarNaive = 2 };
 static int g_variant = -1;
+static int g_xcd_remap = -1;
 static int kernel_variant() {
   if (g_variant < 0) {
     const char* e = getenv("BLCO_KERNEL");
-    g_variant = (e && strcmp(e, "naive") == 0) ? 1 : 0;
+    g_variant = kVarWin;
+    if (e && strcmp(e, "naive") == 0) g_variant = kVarNaive;
+    if (e && strcmp(e, "tile") == 0) g_variant = kVarTile;
+    const char* x = getenv("BLCO_XCD_REMAP");
+    g_xcd_remap = (x && strcmp(x, "1") == 0) ? 1 : 0;
   }
   return g_variant;
 }
@@ -489,11 +691,18 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
   p.wide = t->lay.dims[mode] > ((1ULL << 26) - 1) ? 1 : 0;
   p.scale = scale;
   p.scale_dev = scale_dev;
-  if (kernel_variant() == 1) {
+  const int var = kernel_variant();
+  p.xcd_remap = g_xcd_remap;
+  if (var == kVarNaive) {
     int64_t threads = n * (int64_t)rank;
     int64_t blocks = (threads + 255) / 256;
     KernelFn f = (fdt == BLCO_F32) ? pick_naive<float>(t->lay.N) : pick_naive<uint16_t>(t->lay.N);
     hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, s, p);
+  } else if (var == kVarWin) {
+    int64_t blocks = (n + kWin - 1) / kWin;
+    p.wide = t->lay.dims[mode] > (1ULL << (32 - kWinBits)) ? 1 : 0;
+    KernelFn f = select_win(t->lay.N, rank, fdt);
+    hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(kWin), 0, s, p);
   } else {
     int64_t tiles = (n + 63) / 64;
     int64_t blocks = (tiles + kWaves - 1) / kWaves;

@@ -28,7 +28,8 @@ struct KParams {
   int mode;
   uint32_t shift[8];
   uint32_t mask[8];
-  int wide;                   // target index >= 2^26: sort 64-bit keys
+  int wide;                   // target index too long for 32-bit sort keys
+  int xcd_remap;              // give consecutive windows to the same XCD
   float scale;                // host-side scale of every term
   const double* scale_dev;    // optional device-side scale (one double)
 };

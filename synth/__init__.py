@@ -105,6 +105,9 @@ WORKLOADS = {
     # 3-mode, 2^22 x 2^21 x 2^20 (63 bits: one block), 50M Zipf(1.1), R=32, all modes
     "zipf3": Workload("zipf3", (1 << 22, 1 << 21, 1 << 20), 50_000_000, (_z(1.1),) * 3, "u01",
                       (32,), (0, 1, 2), BASE_SEED * 100 + 1),
+    # same shape with uniform indices: no hot rows (a contention-free reference point)
+    "uniform3": Workload("uniform3", (1 << 22, 1 << 21, 1 << 20), 50_000_000, (U,) * 3, "u01",
+                         (32,), (0, 1, 2), BASE_SEED * 100 + 5),
     # 4-mode, 2^24 x 2^22 x 2^20 x 2^10 (76 bits: blocked on the top 12), 200M, R=32/64
     "zipf4": Workload("zipf4", (1 << 24, 1 << 22, 1 << 20, 1 << 10), 200_000_000,
                       (_z(1.2), _z(1.2), U, U), "lognormal", (32, 64), (0, 1, 2, 3),
