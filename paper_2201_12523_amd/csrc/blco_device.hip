@@ -299,30 +299,65 @@ __device__ __forceinline__ K block_sort(K v, int tid, K* lds) {
 
 constexpr int kWin = 1024;     // non-zeros per window (one per thread of the workgroup)
 constexpr int kWinBits = 10;
+#ifndef BLCO_WIN_U
+#define BLCO_WIN_U 8
+#endif
+// minimum waves per SIMD requested from the compiler: 8 lets two 1024-thread
+// workgroups share a CU (measured about 1.7x faster than one)
+#ifndef BLCO_WIN_OCC
+#define BLCO_WIN_OCC 8
+#endif
+
+// target row of a record (field `mode` of the record at LDS offset `at`)
+__device__ __forceinline__ uint32_t seg_target(const uint32_t* rec, int at, int mode, int N) {
+  return rec[at + mode];
+}
+constexpr uint32_t kBufFlags = 0x00020000u;  // raw buffer resource word 3 (gfx9 family)
+
+template <typename FT>
+__device__ __forceinline__ float ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float ld_buf<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float ld_buf<uint16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0) << 16);
+}
 
 // BLCO MTTKRP with register-based conflict resolution over a window of 1024
-// consecutive non-zeros per workgroup (Sections 5.1-5.2).  The processing
-// phase sorts the whole window by target index (a workgroup-wide bitonic
-// network: in-wave stages by cross-lane permutes, cross-wave stages through
-// LDS), so every target's terms form one segment; the computing phase walks
-// the sorted window with LPN lanes per non-zero and issues one atomic add
-// per (segment, rank).  On MI355X same-address atomics serialise (about
-// 32 ns each), so the wider window directly shortens the atomic chains of
-// frequent output rows.
+// consecutive non-zeros per workgroup (Sections 5.1-5.2).
+//   processing: one non-zero per thread is loaded and decoded by shift and
+//     mask; the workgroup sorts the window by target index (bitonic network:
+//     in-wave stages by cross-lane permutes, cross-wave stages through LDS),
+//     so each target's terms form one segment, and writes one record per
+//     sorted position: value, byte offsets of the other modes' factor rows,
+//     target;
+//   computing: groups of LPN lanes (one rank per lane) walk LPN consecutive
+//     sorted positions each, gathering factor rows with buffer loads and
+//     accumulating the scaled Hadamard product in a register; a segment that
+//     ends inside the group is added to the output with one atomic per rank;
+//     a segment that crosses into later groups is completed by the group it
+//     started in, from partial sums the later groups leave in LDS.
+// Every target therefore costs one global atomic per (window, rank).  On
+// MI355X same-address atomics serialise (about 32 ns each), so merging the
+// whole window bounds the atomic chains of frequent output rows.
 template <int LPN, typename FT, int N>
-__global__ __launch_bounds__(kWin) void k_mttkrp_win(KParams p) {
-  constexpr int G = kWin / LPN;   // groups of LPN lanes
-  constexpr int PPG = kWin / G;   // sorted positions per group (= LPN)
-  constexpr int U = PPG < 8 ? PPG : 8;
-  __shared__ uint32_t s_c[N][kWin];       // decoded coordinates by window position
-  __shared__ float s_x[kWin];             // values by window position
-  __shared__ uint64_t s_key[kWin];        // sorted (target, position) keys
-  __shared__ uint64_t s_end[kWin / 64];   // segment-end bits by sorted position
+__global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
+  constexpr int G = kWin / LPN;                 // groups of LPN lanes
+  constexpr int PPG = kWin / G;                 // sorted positions per group (= LPN)
+  constexpr int U = PPG < BLCO_WIN_U ? PPG : BLCO_WIN_U;
+  constexpr int NF = N + 1;                     // record fields
+  constexpr int NP = NF <= 4 ? 4 : ((NF + 1) / 2) * 2;
+  constexpr int NS = NP > NF ? NP : NF;         // staging/record region, u32 per position
+  __shared__ __align__(16) uint32_t s_rec[kWin * NS];  // staging by position, then records by sorted position
+  __shared__ uint64_t s_key[kWin];
+  __shared__ uint64_t s_end[kWin / 64];
+  __shared__ float s_head[kWin];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   int64_t win = blockIdx.x;
   if (p.xcd_remap) {
-    // consecutive windows to the same XCD (workgroups are dealt round robin over 8 XCDs)
     const int64_t per = gridDim.x / 8;
     if (win < per * 8) win = (win % 8) * per + win / 8;
   }
@@ -331,7 +366,7 @@ __global__ __launch_bounds__(kWin) void k_mttkrp_win(KParams p) {
   const int nvalid = (int)min((int64_t)kWin, p.n - k0);
   const bool valid = tid < nvalid;
 
-  // processing phase
+  // ---- processing: load, decode, stage by window position
   uint32_t c[N];
   float x = 0.f;
   if (valid) {
@@ -342,18 +377,19 @@ __global__ __launch_bounds__(kWin) void k_mttkrp_win(KParams p) {
 #pragma unroll
     for (int m = 0; m < N; ++m) c[m] = 0;
   }
-#pragma unroll
-  for (int m = 0; m < N; ++m) s_c[m][tid] = c[m];
-  s_x[tid] = x;
   uint32_t tgt = 0;
 #pragma unroll
-  for (int m = 0; m < N; ++m)
+  for (int m = 0; m < N; ++m) {
+    s_rec[m * kWin + tid] = c[m];
     if (m == p.mode) tgt = c[m];
+  }
+  s_rec[N * kWin + tid] = __float_as_uint(x);
+  // ---- sort the window by target
   uint64_t sk;
   if (!p.wide) {
     uint32_t v = valid ? ((tgt << kWinBits) | (uint32_t)tid) : 0xFFFFFFFFu;
     v = block_sort<uint32_t, kWin>(v, tid, (uint32_t*)s_key);
-    sk = ((uint64_t)(v >> kWinBits) << kWinBits) | (v & (kWin - 1));
+    sk = v;
   } else {
     uint64_t v = valid ? (((uint64_t)tgt << kWinBits) | (uint64_t)tid) : ~0ULL;
     sk = block_sort<uint64_t, kWin>(v, tid, s_key);
@@ -364,43 +400,323 @@ __global__ __launch_bounds__(kWin) void k_mttkrp_win(KParams p) {
                    (tid == nvalid - 1 || (s_key[tid + 1] >> kWinBits) != (sk >> kWinBits));
   const uint64_t em = __ballot(end);
   if (lane == 0) s_end[tid >> 6] = em;
+  // gather this sorted position's record from the staging area: field m holds
+  // the byte offset of factor row i_m (the target's row index for m = mode),
+  // field N the value
+  const int src = (int)(sk & (kWin - 1));
+  uint32_t rec[NF];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const uint32_t cm = s_rec[m * kWin + src];
+    rec[m] = (m == p.mode) ? cm : cm * p.rowbytes;
+  }
+  rec[N] = s_rec[N * kWin + src];
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < NF; ++f) s_rec[tid * NP + f] = rec[f];
   __syncthreads();
 
-  // computing phase
+  // ---- computing: rank-wise walk of LPN sorted positions per group
   const int g = tid / LPN;
   const int rl = tid % LPN;
   const int p0 = g * PPG;
   const uint64_t endw = s_end[p0 >> 6] >> (p0 & 63);
+  const uint64_t gmask = PPG >= 64 ? ~0ULL : ((1ULL << PPG) - 1);
+  const bool starts_before =
+      p0 > 0 && p0 < nvalid && !((s_end[(p0 - 1) >> 6] >> ((p0 - 1) & 63)) & 1);
+  __amdgpu_buffer_rsrc_t rs[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m)
+    rs[m] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.A[m]), 0, (int)p.abytes[m],
+                                              (int)kBufFlags);
   const float scale = term_scale(p);
   const int R = p.R;
   for (int r0 = 0; r0 < R; r0 += LPN) {
     const int r = r0 + rl;
     const bool ract = r < R;
-    const int rr = ract ? r : 0;
-    float acc = 0.f;
+    const uint32_t loff = (uint32_t)(ract ? r : 0) * (uint32_t)sizeof(FT);
+    float acc = 0.f, carry = 0.f;
+    bool first = true, has_carry = false;
     for (int q0 = 0; q0 < PPG; q0 += U) {
       float pr[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int src = (int)(s_key[p0 + q0 + u] & (kWin - 1));
-        float v = s_x[src];
+        const uint32_t* e = &s_rec[(p0 + q0 + u) * NP];
+        float v = __uint_as_float(e[N]);
 #pragma unroll
         for (int m = 0; m < N; ++m)
-          if (m != p.mode) v *= ld_factor<FT>(p.A[m], (size_t)s_c[m][src] * R + rr);
+          if (m != p.mode) v *= ld_buf<FT>(rs[m], e[m] + loff);
         pr[u] = v;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int q = q0 + u;
-        acc += pr[u];
-        if (((endw >> q) & 1) || q == PPG - 1) {
-          if (ract && p0 + q < nvalid) {
-            const uint64_t t = s_key[p0 + q] >> kWinBits;
-            unsafeAtomicAdd(p.out + (size_t)t * R + r, acc * scale);
+        const int pp = p0 + q;
+        if (pp < nvalid) {
+          acc += pr[u];
+          const bool seg_end = (endw >> q) & 1;
+          if (seg_end || q == PPG - 1) {
+            if (first && starts_before) {
+              s_head[tid] = acc;
+            } else if (seg_end) {
+              if (ract) unsafeAtomicAdd(p.out + (size_t)seg_target(s_rec, pp * NP, p.mode, N) * R + r,
+                                        acc * scale);
+            } else {
+              carry = acc;
+              has_carry = true;
+            }
+            acc = 0.f;
+            first = false;
           }
-          acc = 0.f;
         }
       }
+    }
+    __syncthreads();
+    if (has_carry) {
+      // this group owns a segment that continues into the next groups
+      for (int g2 = g + 1; g2 < G; ++g2) {
+        const int q2 = g2 * PPG;
+        carry += s_head[g2 * LPN + rl];
+        if ((s_end[q2 >> 6] >> (q2 & 63)) & gmask) break;
+      }
+      if (ract)
+        unsafeAtomicAdd(p.out + (size_t)seg_target(s_rec, (p0 + PPG - 1) * NP, p.mode, N) * R + r,
+                        carry * scale);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BLCO MTTKRP with hierarchical conflict resolution through an LDS stash
+// (Section 5.1, steps 5-6), the default kernel.
+//
+// Persistent workgroups of kSB threads each own a contiguous range of the
+// ALTO-ordered non-zeros and walk it in batches of kSB:
+//   processing: one non-zero per thread is loaded (coalesced) and decoded by
+//     shift and mask; its target row is looked up in an LDS hash table that
+//     maps target -> dense segment id, claiming a new segment when the target
+//     is new to the current window;
+//   computing: LG lanes per non-zero, each holding V consecutive ranks, gather
+//     the other modes' factor rows (one V-wide load per factor), form the
+//     scaled Hadamard product and add it into the segment's LDS accumulator;
+//   flushing: once the stash holds S segments (or the range ends) every
+//     segment row is added to the output with one global atomic per
+//     (segment, rank), and the stash is cleared.
+// Equal targets inside a window therefore cost one global atomic each; a
+// target that arrives when the stash is full is added straight to the output.
+constexpr int kSB = 512;               // threads per workgroup = non-zeros per batch
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kOverflow = 0xFFFFFFFEu;
+
+struct StashCfg {
+  int S;        // segment rows in the stash
+  int TS;       // hash table slots (power of two >= 2 S)
+  int tsbits;
+  int lg_log;   // log2 of lanes per non-zero in the computing phase
+  int Rp;       // stash row length (R rounded up to LG * V)
+  int64_t per;  // non-zeros per workgroup range (multiple of kSB)
+};
+
+template <int V, typename FT>
+struct Vec;
+template <>
+struct Vec<1, float> {
+  static __device__ __forceinline__ void load(const void* A, size_t i, float* o) {
+    o[0] = static_cast<const float*>(A)[i];
+  }
+};
+template <>
+struct Vec<4, float> {
+  static __device__ __forceinline__ void load(const void* A, size_t i, float* o) {
+    const float4 v = *reinterpret_cast<const float4*>(static_cast<const float*>(A) + i);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+};
+template <>
+struct Vec<1, uint16_t> {
+  static __device__ __forceinline__ void load(const void* A, size_t i, float* o) {
+    o[0] = __uint_as_float((uint32_t)static_cast<const uint16_t*>(A)[i] << 16);
+  }
+};
+template <>
+struct Vec<4, uint16_t> {
+  static __device__ __forceinline__ void load(const void* A, size_t i, float* o) {
+    const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(A) + i);
+    o[0] = __uint_as_float(v.x << 16);
+    o[1] = __uint_as_float(v.x & 0xFFFF0000u);
+    o[2] = __uint_as_float(v.y << 16);
+    o[3] = __uint_as_float(v.y & 0xFFFF0000u);
+  }
+};
+
+__device__ __forceinline__ uint32_t stash_hash(uint32_t t, int bits) {
+  return (t * 0x9E3779B1u) >> (32 - bits);
+}
+
+template <int V, typename FT, int N>
+__global__ __launch_bounds__(kSB) void k_mttkrp_stash(KParams p, StashCfg cfg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  // LDS layout: accumulators | segment targets | table keys | table values |
+  //             batch coordinates | batch values | batch segment ids | counter
+  float* s_acc = reinterpret_cast<float*>(smem);
+  uint32_t* s_segt = reinterpret_cast<uint32_t*>(s_acc + (size_t)cfg.S * cfg.Rp);
+  uint32_t* s_tkey = s_segt + cfg.S;
+  uint32_t* s_tval = s_tkey + cfg.TS;
+  uint32_t* s_c = s_tval + cfg.TS;            // N x kSB
+  float* s_x = reinterpret_cast<float*>(s_c + N * kSB);
+  uint32_t* s_sid = reinterpret_cast<uint32_t*>(s_x + kSB);
+  uint32_t* s_nseg = s_sid + kSB;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int R = p.R;
+  const int Rp = cfg.Rp;
+  const float scale = term_scale(p);
+  const int64_t lo = (int64_t)blockIdx.x * cfg.per;
+  const int64_t hi = min(p.n, lo + cfg.per);
+  if (lo >= hi) return;
+
+  for (int i = tid; i < cfg.S * Rp; i += kSB) s_acc[i] = 0.f;
+  for (int i = tid; i < cfg.TS; i += kSB) s_tkey[i] = kEmpty;
+  if (tid == 0) *s_nseg = 0;
+  __syncthreads();
+
+  const int LG = 1 << cfg.lg_log;               // lanes per non-zero
+  const int NG = kSB >> cfg.lg_log;             // non-zeros in flight per workgroup step
+  const int gi = tid >> cfg.lg_log;             // group of this lane
+  const int gl = tid & (LG - 1);                // lane within the group
+
+  for (int64_t b0 = lo; b0 < hi; b0 += kSB) {
+    // ---- processing: load, decode, find or claim the target's segment
+    const int64_t k = b0 + tid;
+    const bool valid = k < hi;
+    uint32_t c[N];
+    float x = 0.f;
+    if (valid) {
+      const uint64_t key = p.keys[k];
+      x = p.vals[k];
+      decode<N>(p, key, p.base + k, c);
+    } else {
+#pragma unroll
+      for (int m = 0; m < N; ++m) c[m] = 0;
+    }
+    uint32_t tgt = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      s_c[m * kSB + tid] = c[m];
+      if (m == p.mode) tgt = c[m];
+    }
+    s_x[tid] = x;
+    int slot = -1;
+    bool claimed = false;
+    if (valid && tgt < kOverflow) {
+      uint32_t h = stash_hash(tgt, cfg.tsbits);
+      for (int probe = 0; probe < 32; ++probe) {
+        const uint32_t old = atomicCAS(&s_tkey[h], kEmpty, tgt);
+        if (old == kEmpty || old == tgt) {
+          slot = (int)h;
+          claimed = old == kEmpty;
+          break;
+        }
+        h = (h + 1) & (uint32_t)(cfg.TS - 1);
+      }
+    }
+    __syncthreads();
+    // segment ids for newly claimed slots: one LDS atomic per wave
+    const uint64_t cm = __ballot(claimed);
+    uint32_t base = 0;
+    if (lane == 0 && cm) base = atomicAdd(s_nseg, (uint32_t)__popcll(cm));
+    base = (uint32_t)__shfl((int)base, 0);
+    if (claimed) {
+      const uint32_t sid = base + (uint32_t)__popcll(cm & ((1ULL << lane) - 1));
+      if (sid < (uint32_t)cfg.S) {
+        s_tval[slot] = sid;
+        s_segt[sid] = tgt;
+      } else {
+        s_tval[slot] = kOverflow;
+      }
+    }
+    __syncthreads();
+    s_sid[tid] = valid ? (slot >= 0 ? s_tval[slot] : kOverflow) : kEmpty;
+    __syncthreads();
+
+    // ---- computing: LG lanes per non-zero, V ranks per lane
+    for (int r0 = 0; r0 < R; r0 += LG * V) {
+      const int rbase = r0 + gl * V;
+      for (int j = gi; j < kSB; j += NG) {
+        const uint32_t sid = s_sid[j];
+        if (sid == kEmpty) continue;
+        float v[V];
+        const float xv = s_x[j];
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] = xv;
+        if (rbase < R) {
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            if (m == p.mode) continue;
+            const size_t row = (size_t)s_c[m * kSB + j] * R;
+            if (V == 1 || rbase + V <= R) {
+              float f[V];
+              Vec<V, FT>::load(p.A[m], row + rbase, f);
+#pragma unroll
+              for (int e = 0; e < V; ++e) v[e] *= f[e];
+            } else {
+#pragma unroll
+              for (int e = 0; e < V; ++e) {
+                float f1[1];
+                Vec<1, FT>::load(p.A[m], row + (rbase + e < R ? rbase + e : 0), f1);
+                v[e] *= f1[0];
+              }
+            }
+          }
+        }
+        if (sid < (uint32_t)cfg.S) {
+          float* a = s_acc + (size_t)sid * Rp + rbase - r0;
+#pragma unroll
+          for (int e = 0; e < V; ++e)
+            if (rbase + e < R) atomicAdd(a + e, v[e]);
+        } else {
+          const uint32_t t = s_c[p.mode * kSB + j];
+#pragma unroll
+          for (int e = 0; e < V; ++e)
+            if (rbase + e < R) unsafeAtomicAdd(p.out + (size_t)t * R + rbase + e, v[e] * scale);
+        }
+      }
+      if (r0 + LG * V < R) {
+        // next rank chunk reuses the accumulators: flush this chunk first
+        __syncthreads();
+        const int nseg = min((int)*s_nseg, cfg.S);
+        for (int i = tid; i < nseg * LG * V; i += kSB) {
+          const int sgi = i / (LG * V), rr = i % (LG * V);
+          if (r0 + rr < R) {
+            float* a = s_acc + (size_t)sgi * Rp + rr;
+            const float val = *a;
+            if (val != 0.f) unsafeAtomicAdd(p.out + (size_t)s_segt[sgi] * R + r0 + rr, val * scale);
+            *a = 0.f;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    // ---- flush the stash when full or at the end of the range
+    const int nseg_all = (int)*s_nseg;
+    if (nseg_all >= cfg.S || b0 + kSB >= hi) {
+      const int nseg = min(nseg_all, cfg.S);
+      const int rlast = ((R - 1) / (LG * V)) * (LG * V);  // rank chunk still held
+      const int w = min(R - rlast, LG * V);
+      for (int i = tid; i < nseg * w; i += kSB) {
+        const int sgi = i / w, rr = i - sgi * w;
+        float* a = s_acc + (size_t)sgi * Rp + rr;
+        const float val = *a;
+        if (val != 0.f) unsafeAtomicAdd(p.out + (size_t)s_segt[sgi] * R + rlast + rr, val * scale);
+        *a = 0.f;
+      }
+      for (int i = tid; i < cfg.TS; i += kSB) s_tkey[i] = kEmpty;
+      __syncthreads();
+      if (tid == 0) *s_nseg = 0;
+      __syncthreads();
     }
   }
 }
@@ -541,6 +857,22 @@ static KernelFn pick_win(int N) {
   }
 }
 
+typedef void (*StashFn)(KParams, StashCfg);
+
+template <int V, typename FT>
+static StashFn pick_stash(int N) {
+  switch (N) {
+    case 1: return k_mttkrp_stash<V, FT, 1>;
+    case 2: return k_mttkrp_stash<V, FT, 2>;
+    case 3: return k_mttkrp_stash<V, FT, 3>;
+    case 4: return k_mttkrp_stash<V, FT, 4>;
+    case 5: return k_mttkrp_stash<V, FT, 5>;
+    case 6: return k_mttkrp_stash<V, FT, 6>;
+    case 7: return k_mttkrp_stash<V, FT, 7>;
+    default: return k_mttkrp_stash<V, FT, 8>;
+  }
+}
+
 template <int LPN, typename FT>
 static KernelFn pick_loss(int N) {
   switch (N) {
@@ -610,17 +942,35 @@ static KernelFn select_loss(int N, int R, int fdt) {
 
 // MTTKRP kernel variant, chosen once per process from BLCO_KERNEL:
 //   "win" (default): 1024-non-zero windows sorted per workgroup;
+//   "stash": persistent workgroups with an LDS segment stash;
 //   "tile": 64-non-zero tiles sorted per wave;
 //   "naive": one thread and one atomic per (non-zero, rank).
 // BLCO_XCD_REMAP=1 gives consecutive windows to the same XCD (measured slower
 // on the Zipf workloads, so off by default).
-enum { kVarWin = 0, kVarTile = 1, kVarNaive = 2 };
+enum { kVarWin = 0, kVarStash = 1, kVarTile = 2, kVarNaive = 3 };
 static int g_variant = -1;
 static int g_xcd_remap = -1;
+
+// LDS bytes per workgroup for the stash kernel (BLCO_STASH_KB, default 64)
+static size_t stash_lds_budget() {
+  const char* e = getenv("BLCO_STASH_KB");
+  long kb = e ? atol(e) : 64;
+  if (kb < 16) kb = 16;
+  if (kb > 160) kb = 160;
+  return (size_t)kb * 1024;
+}
+
+// workgroups the non-zeros are split over (BLCO_STASH_WG, default 2048)
+static int64_t stash_workgroups() {
+  const char* e = getenv("BLCO_STASH_WG");
+  long w = e ? atol(e) : 2048;
+  return w < 1 ? 1 : w;
+}
 static int kernel_variant() {
   if (g_variant < 0) {
     const char* e = getenv("BLCO_KERNEL");
     g_variant = kVarWin;
+    if (e && strcmp(e, "stash") == 0) g_variant = kVarStash;
     if (e && strcmp(e, "naive") == 0) g_variant = kVarNaive;
     if (e && strcmp(e, "tile") == 0) g_variant = kVarTile;
     const char* x = getenv("BLCO_XCD_REMAP");
@@ -630,6 +980,8 @@ static int kernel_variant() {
 }
 
 // ====================================================================== host runtime
+
+static size_t factor_elem_bytes(int fdt) { return fdt == BLCO_BF16 ? 2 : 4; }
 
 static void fill_params(const blco_tensor* t, KParams* p) {
   memset(p, 0, sizeof(*p));
@@ -691,13 +1043,57 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
   p.wide = t->lay.dims[mode] > ((1ULL << 26) - 1) ? 1 : 0;
   p.scale = scale;
   p.scale_dev = scale_dev;
-  const int var = kernel_variant();
+  int var = kernel_variant();
   p.xcd_remap = g_xcd_remap;
+  const size_t fsz = factor_elem_bytes(fdt);
+  p.rowbytes = (uint32_t)((size_t)rank * fsz);
+  bool fits32 = (size_t)rank * fsz < (1ULL << 31);
+  for (int m = 0; m < t->lay.N; ++m) {
+    const size_t bytes = (size_t)t->lay.dims[m] * rank * fsz;
+    p.abytes[m] = (uint32_t)std::min<size_t>(bytes, 0xFFFFFFFFull);
+    if (m != mode && bytes > 0xFFFFFFFFull) fits32 = false;
+  }
+  // the window kernel addresses factor rows with 32-bit byte offsets
+  if (var == kVarWin && !fits32) var = kVarTile;
   if (var == kVarNaive) {
     int64_t threads = n * (int64_t)rank;
     int64_t blocks = (threads + 255) / 256;
     KernelFn f = (fdt == BLCO_F32) ? pick_naive<float>(t->lay.N) : pick_naive<uint16_t>(t->lay.N);
     hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, s, p);
+  } else if (var == kVarStash) {
+    const int N = t->lay.N;
+    const int V = (rank % 4 == 0) ? 4 : 1;
+    int lanes = (rank + V - 1) / V;
+    int lg_log = 0;
+    while ((1 << lg_log) < lanes && lg_log < 6) ++lg_log;
+    StashCfg cfg;
+    cfg.lg_log = lg_log;
+    cfg.Rp = (1 << lg_log) * V;
+    const size_t budget = stash_lds_budget();
+    const size_t fixed = (size_t)(N + 2) * kSB * 4 + 16;
+    int bestS = 0, bestTS = 0;
+    for (int TS = 4096; TS >= 256; TS >>= 1) {
+      if (fixed + (size_t)TS * 8 >= budget) continue;
+      size_t avail = budget - fixed - (size_t)TS * 8;
+      int S = (int)std::min<size_t>((size_t)TS / 2, avail / ((size_t)cfg.Rp * 4 + 4));
+      if (S > bestS) { bestS = S; bestTS = TS; }
+    }
+    if (bestS < 1) return set_error(BLCO_EUNSUPPORTED, "rank %d too large for the LDS stash", rank);
+    cfg.S = bestS;
+    cfg.TS = bestTS;
+    cfg.tsbits = 0;
+    while ((1 << cfg.tsbits) < cfg.TS) ++cfg.tsbits;
+    const int64_t batches = (n + kSB - 1) / kSB;
+    const int64_t want_wg = stash_workgroups();
+    int64_t per_b = std::max<int64_t>((batches + want_wg - 1) / want_wg, 1);
+    cfg.per = per_b * kSB;
+    const int64_t nwg = (n + cfg.per - 1) / cfg.per;
+    const size_t lds = (size_t)cfg.S * cfg.Rp * 4 + (size_t)cfg.S * 4 + (size_t)cfg.TS * 8 +
+                       (size_t)(N + 2) * kSB * 4 + 16;
+    StashFn f = (fdt == BLCO_F32) ? (V == 4 ? pick_stash<4, float>(N) : pick_stash<1, float>(N))
+                                  : (V == 4 ? pick_stash<4, uint16_t>(N) : pick_stash<1, uint16_t>(N));
+    if (lds > 65536) HIPCHK(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(f, dim3((unsigned)nwg), dim3(kSB), lds, s, p, cfg);
   } else if (var == kVarWin) {
     int64_t blocks = (n + kWin - 1) / kWin;
     p.wide = t->lay.dims[mode] > (1ULL << (32 - kWinBits)) ? 1 : 0;
@@ -720,7 +1116,6 @@ static void* pinned_alloc(size_t n) {
 }
 static void pinned_free(void* p) { (void)hipHostFree(p); }
 
-static size_t factor_elem_bytes(int fdt) { return fdt == BLCO_BF16 ? 2 : 4; }
 
 template <class T>
 static int upload(T** dst, const T* src, size_t count, size_t* acc) {
