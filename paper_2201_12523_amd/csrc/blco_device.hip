@@ -308,6 +308,45 @@ constexpr int kWinBits = 10;
 #define BLCO_WIN_OCC 8
 #endif
 
+#ifndef BLCO_WIN_BITONIC
+#define BLCO_WIN_BITONIC 0
+#endif
+constexpr int kBucketBits = 12;
+constexpr int kBuckets = 1 << kBucketBits;   // hash buckets per window
+
+// In-place exclusive prefix sum of NB counters in LDS by a workgroup of NT
+// threads (NB a multiple of NT): per-thread serial sums, a wave scan by
+// cross-lane shifts, and one LDS pass over the per-wave totals.
+template <int NB, int NT>
+__device__ __forceinline__ void block_exclusive_scan(uint32_t* a, int tid, uint32_t* wsum) {
+  constexpr int PER = NB / NT;
+  uint32_t v[PER];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    v[i] = a[tid * PER + i];
+    tot += v[i];
+  }
+  const int lane = tid & 63;
+  uint32_t inc = tot;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
+    if (lane >= off) inc += o;
+  }
+  if (lane == 63) wsum[tid >> 6] = inc;
+  __syncthreads();
+  uint32_t wbase = 0;
+  for (int w = 0; w < (tid >> 6); ++w) wbase += wsum[w];
+  uint32_t run = wbase + inc - tot;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    a[tid * PER + i] = run;
+    run += v[i];
+  }
+  __syncthreads();
+}
+
 // target row of a record (field `mode` of the record at LDS offset `at`)
 __device__ __forceinline__ uint32_t seg_target(const uint32_t* rec, int at, int mode, int N) {
   return rec[at + mode];
@@ -350,10 +389,15 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   constexpr int NF = N + 1;                     // record fields
   constexpr int NP = NF <= 4 ? 4 : ((NF + 1) / 2) * 2;
   constexpr int NS = NP > NF ? NP : NF;         // staging/record region, u32 per position
-  __shared__ __align__(16) uint32_t s_rec[kWin * NS];  // staging by position, then records by sorted position
-  __shared__ uint64_t s_key[kWin];
+  __shared__ __align__(16) uint32_t s_rec[kWin * NS];  // records by grouped position
   __shared__ uint64_t s_end[kWin / 64];
   __shared__ float s_head[kWin];
+#if BLCO_WIN_BITONIC
+  __shared__ uint64_t s_key[kWin];
+#else
+  __shared__ uint32_t s_hist[kBuckets];
+  __shared__ uint32_t s_wsum[kWin / 64];
+#endif
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   int64_t win = blockIdx.x;
@@ -379,10 +423,11 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   }
   uint32_t tgt = 0;
 #pragma unroll
-  for (int m = 0; m < N; ++m) {
-    s_rec[m * kWin + tid] = c[m];
+  for (int m = 0; m < N; ++m)
     if (m == p.mode) tgt = c[m];
-  }
+#if BLCO_WIN_BITONIC
+#pragma unroll
+  for (int m = 0; m < N; ++m) s_rec[m * kWin + tid] = c[m];
   s_rec[N * kWin + tid] = __float_as_uint(x);
   // ---- sort the window by target
   uint64_t sk;
@@ -415,6 +460,33 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
 #pragma unroll
   for (int f = 0; f < NF; ++f) s_rec[tid * NP + f] = rec[f];
   __syncthreads();
+#else
+  // ---- group the window by target: counting sort on a hash of the target.
+  // Equal targets land in one bucket, so they become one contiguous run; two
+  // targets sharing a bucket may interleave, which only splits a segment.
+  for (int i = tid; i < kBuckets; i += kWin) s_hist[i] = 0;
+  __syncthreads();
+  const uint32_t bkt = (tgt * 0x9E3779B1u) >> (32 - kBucketBits);
+  uint32_t rank = 0;
+  if (valid) rank = atomicAdd(&s_hist[bkt], 1u);
+  __syncthreads();
+  block_exclusive_scan<kBuckets, kWin>(s_hist, tid, s_wsum);
+  // record of this non-zero at its grouped position: field m holds the byte
+  // offset of factor row i_m (the target's row index for m = mode), field N
+  // the value; padding lanes keep their own (trailing) positions
+  const int pos = valid ? (int)(s_hist[bkt] + rank) : tid;
+#pragma unroll
+  for (int m = 0; m < N; ++m) s_rec[pos * NP + m] = (m == p.mode) ? c[m] : c[m] * p.rowbytes;
+  s_rec[pos * NP + N] = __float_as_uint(x);
+  __syncthreads();
+  {
+    const uint32_t t0 = s_rec[tid * NP + p.mode];
+    const bool end = (tid < nvalid) && (tid == nvalid - 1 || s_rec[(tid + 1) * NP + p.mode] != t0);
+    const uint64_t em = __ballot(end);
+    if (lane == 0) s_end[tid >> 6] = em;
+  }
+  __syncthreads();
+#endif
 
   // ---- computing: rank-wise walk of LPN sorted positions per group
   const int g = tid / LPN;
