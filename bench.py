@@ -1,15 +1,26 @@
-"""Benchmark: all-mode BLCO sparse MTTKRP on one MI355X.
+"""Benchmark: BLCO sparse MTTKRP on one MI355X.
 
-Workload (default): 3-mode tensor 2^22 x 2^21 x 2^20 (63 key bits, one block),
-50M distinct non-zeros with per-mode Zipf(1.1) indices, U(0,1) values, rank-32
-N(0,1) factors; MTTKRP in all three modes from one BLCO copy.  A step is one
-MTTKRP per mode (output zero-fill included) with fp32 factors; inputs are
+Default workload (``zipf3``): 3-mode tensor 2^22 x 2^21 x 2^20 (63 key bits, one
+block), 50M distinct non-zeros with per-mode Zipf(1.1) indices, U(0,1) values,
+rank-32 N(0,1) factors; MTTKRP in all three modes from one BLCO copy.  A step is
+one MTTKRP per mode (output zero-fill included) with fp32 factors; inputs are
 resident in device memory before timing starts.  The bf16-factor form is timed
-beside it, and both are checked against the fp64 oracle on sampled rows.
+beside it, and both are checked against the fp64 oracle on sampled rows in the
+CPU-baseline leg.
+
+Other legs (``--workload``):
+  zipf4    4-mode 2^24 x 2^22 x 2^20 x 2^10 (76 bits, blocked on the top 12),
+           200M non-zeros, R = 32 and 64, fp32 and bf16 factors;
+  oom3     3-mode 2^23 x 2^23 x 2^17, 1.5B non-zeros in pinned host memory,
+           streamed under an 8 GB device budget; copy/compute overlap reported;
+  cpgrad4  sparse CP loss + gradient step, 4-mode 2^20 x 2^18 x 2^16 x 2^12,
+           80M non-zeros holding a planted rank-8 model plus noise, R = 32;
+  uniform3 the zipf3 shape with uniform indices.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,10 +32,354 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "MTTKRP Gnnz/s per mode & % HBM peak; bf16 vs fp32 factors at stated rel error"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mttkrp_win_zipf3.txt")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("blco_device.hip", "blco_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2201_12523_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, if it matches this kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+class Timer:
+    """Average milliseconds of `fn` over `steps` calls, with HIP events on torch's stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def __call__(self, fn, steps, warmup=1):
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(steps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+
+def sampled_rows(rng, I, k=120):
+    return np.unique(np.concatenate([np.arange(min(8, I)), rng.integers(0, I, k), [I - 1]])
+                     ).astype(np.uint32)
+
+
+def row_errors(oracle, blco, torch, T, coords, vals, A_ref, F, outs, dims, modes, rng, dev):
+    """Max / median of |gpu - oracle| / sum|terms| over sampled rows of each mode."""
+    worst, meds = 0.0, []
+    for n in modes:
+        o = blco.mttkrp(T, n, F, out=outs[n])
+        rows = sampled_rows(rng, dims[n])
+        M, S = oracle.mttkrp_rows_f32(coords, vals, A_ref, n, rows, dims)
+        got = o[torch.from_numpy(rows.astype(np.int64)).to(dev)].cpu().numpy().astype(np.float64)
+        nz = S > 0
+        e = np.abs(got - M)[nz] / S[nz]
+        worst = max(worst, float(e.max()) if e.size else 0.0)
+        meds.append(float(np.median(e)) if e.size else 0.0)
+    return {"max": worst, "median": float(np.median(meds))}
+
+
+def cpu_oracle_rate(oracle, coords, vals, A, sample, modes):
+    """The fp64 oracle, single thread, over the first `sample` non-zeros of every mode."""
+    S = min(sample, len(vals))
+    cs = [c[:S] for c in coords]
+    Ad = [a.astype(np.float64) for a in A]
+    t0 = time.time()
+    for n in modes:
+        oracle.mttkrp(cs, vals[:S], Ad, n)
+    dt = time.time() - t0
+    return {"value": S * len(modes) / dt / 1e9, "unit": "Gnnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {S} non-zeros of the workload, {len(modes)} modes, fp64, "
+                      f"single thread, {dt:.1f}s"}
+
+
+def describe(w, nnz):
+    dist = "/".join(f"{d[0]}({d[1]})" if d[0] == "zipf" else d[0] for d in w.index_dist)
+    vals = {"u01": "U(0,1)", "lognormal": "lognormal(0,1)", "cp8": "rank-8 CP model + N(0,0.01)"}
+    return (f"{w.name}: {len(w.dims)}-mode {'x'.join(str(d) for d in w.dims)}, {nnz} distinct "
+            f"non-zeros, per-mode {dist} indices, {vals[w.value_dist]} values, ranks "
+            f"{'/'.join(str(r) for r in w.ranks)}")
+
+
+def base_result(args, w, nnz, value, ms_step, dtype="f32"):
+    return {
+        "metric": METRIC, "value": value, "unit": "Gnnz/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": describe(w, nnz), "nnz": nnz, "dims": list(w.dims),
+                   "modes": len(w.dims)},
+    }
+
+
+# --------------------------------------------------------------------------- legs
+
+def leg_inmemory(args, torch, blco, synth, w):
+    dev = torch.device("cuda:0")
+    timer = Timer(torch)
+    t0 = time.time()
+    coords, vals = synth.workload_tensor(w, nnz=args.nnz, log=log)
+    nnz = len(vals)
+    log(f"generated {nnz} non-zeros in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    T = blco.build(coords, vals, w.dims)
+    build_s = time.time() - t0
+    inf = T.info()
+    log(f"built BLCO in {build_s:.2f}s: T={inf['total_bits']} bits, {inf['nblocks']} block(s), "
+        f"{inf['nruns']} run(s)")
+    N = len(w.dims)
+    modes = list(range(N))
+    distinct = [int(np.count_nonzero(np.bincount(c, minlength=d))) for c, d in zip(coords, w.dims)]
+    results = {}
+    head = None
+    for R in w.ranks:
+        A = synth.workload_factors(w, R)
+        F32 = [torch.from_numpy(a).to(dev) for a in A]
+        BF16 = [blco.cast_bf16(f) for f in F32]
+        outs = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in w.dims]
+        torch.cuda.synchronize()
+        for tag, F in (("fp32", F32), ("bf16", BF16)):
+            def step(F=F, outs=outs):
+                for n in modes:
+                    blco.mttkrp(T, n, F, out=outs[n])
+            ms_step = timer(step, args.steps, args.warmup)
+            call = [timer(lambda n=n: blco.mttkrp(T, n, F, out=outs[n]), args.steps) for n in modes]
+            kern = [timer(lambda n=n: blco.mttkrp_acc(T, n, F, outs[n]), args.steps) for n in modes]
+            sf = 4 if tag == "fp32" else 2
+            per_nnz = 12 + (N - 1) * R * sf
+            results[f"R{R}_{tag}"] = {
+                "ms_per_step": ms_step, "gnnz_s": nnz * N / (ms_step * 1e-3) / 1e9,
+                "call_ms": call, "kernel_ms": kern,
+                "per_mode_gnnz_s": [nnz / (x * 1e-3) / 1e9 for x in call],
+                "bytes_per_nnz": per_nnz,
+                "kernel_gbs": [nnz * per_nnz / (x * 1e-3) / 1e9 for x in kern],
+            }
+            log(f"R={R} {tag}: all-mode step {ms_step:.3f} ms, kernel ms/mode "
+                f"{[round(x, 3) for x in kern]}")
+            if head is None:
+                head = (R, ms_step, kern, per_nnz, A, F32, BF16, outs)
+    R, ms_step, kern, per_nnz, A, F32, BF16, outs = head
+    avg_kernel_ms = float(np.mean(kern))
+    achieved = nnz * per_nnz / (avg_kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic() if w.name == "zipf3" and args.nnz is None else None
+    compulsory = [nnz * 12 + sum(distinct[m] * R * 4 for m in modes if m != n) +
+                  2 * w.dims[n] * R * 4 for n in modes]
+    res = base_result(args, w, nnz, nnz * N / (ms_step * 1e-3) / 1e9, ms_step)
+    res["config"].update({"rank": R, "key_bits": inf["total_bits"], "blocks": inf["nblocks"]})
+    res["roofline"] = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        "kernel": f"k_mttkrp_win<{32 if R <= 32 else 64}, float, {N}>",
+        "bytes_per_nnz": per_nnz, "avg_kernel_ms": avg_kernel_ms,
+        "compulsory_bytes_per_launch": compulsory,
+    }
+    res["per_config"] = results
+    res["distinct_indices"] = distinct
+    res["build_s"] = build_s
+    res["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        res["cpu_baseline"] = cpu_oracle_rate(oracle, coords, vals, A, args.cpu_sample_nnz, modes)
+        log(f"cpu oracle: {res['cpu_baseline']['value']:.4f} Gnnz/s")
+        rng = np.random.default_rng(7)
+        errs = {}
+        for R in w.ranks:
+            if R == head[0]:
+                A_, F32_, BF16_, outs_ = A, F32, BF16, outs
+            else:
+                A_ = synth.workload_factors(w, R)
+                F32_ = [torch.from_numpy(a).to(dev) for a in A_]
+                BF16_ = [blco.cast_bf16(f) for f in F32_]
+                outs_ = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in w.dims]
+            Ab = [oracle.bf16_round(a) for a in A_]
+            errs[f"R{R}_fp32"] = row_errors(oracle, blco, torch, T, coords, vals, A_, F32_, outs_,
+                                            w.dims, modes, rng, dev)
+            errs[f"R{R}_bf16"] = row_errors(oracle, blco, torch, T, coords, vals, Ab, BF16_, outs_,
+                                            w.dims, modes, rng, dev)
+            errs[f"R{R}_bf16_vs_fp32"] = row_errors(oracle, blco, torch, T, coords, vals, A_,
+                                                    BF16_, outs_, w.dims, modes, rng, dev)
+        res["errors"] = errs
+        log(f"errors: {errs}")
+    return res
+
+
+def leg_oom(args, torch, blco, synth, w):
+    dev = torch.device("cuda:0")
+    timer = Timer(torch)
+    t0 = time.time()
+    coords, vals = synth.workload_tensor(w, nnz=args.nnz, log=log)
+    nnz = len(vals)
+    log(f"generated {nnz} non-zeros in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    T = blco.build(coords, vals, w.dims, placement="pinned")
+    build_s = time.time() - t0
+    log(f"built pinned BLCO in {build_s:.1f}s")
+    N = len(w.dims)
+    modes = list(range(N))
+    R = w.ranks[0]
+    A = synth.workload_factors(w, R)
+    F = [torch.from_numpy(a).to(dev) for a in A]
+    outs = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in w.dims]
+    budget = args.budget or w.budget_bytes
+    per = []
+    for n in modes:
+        ms = timer(lambda n=n: blco.mttkrp_stream(T, n, F, out=outs[n], device_budget=budget),
+                   args.steps, args.warmup)
+        inf = T.info()
+        copy_ms, kern_ms = inf["stream_copy_ms"], inf["stream_kernel_ms"]
+        tot_ms = inf["stream_total_ms"]
+        overlap = (copy_ms + kern_ms - tot_ms) / max(min(copy_ms, kern_ms), 1e-9)
+        per.append({"mode": n, "call_ms": ms, "overall_gnnz_s": nnz / (ms * 1e-3) / 1e9,
+                    "in_memory_gnnz_s": nnz / (kern_ms * 1e-3) / 1e9,
+                    "h2d_gbs": nnz * 12 / (copy_ms * 1e-3) / 1e9,
+                    "copy_ms": copy_ms, "kernel_ms": kern_ms, "total_ms": tot_ms,
+                    "overlap": overlap, "chunks": inf["stream_chunks"],
+                    "chunk_nnz": inf["stream_chunk_nnz"],
+                    "peak_device_bytes": inf["stream_peak_bytes"]})
+        log(f"mode {n}: {ms:.1f} ms/call, copy {copy_ms:.1f} ms, kernels {kern_ms:.1f} ms, "
+            f"span {tot_ms:.1f} ms, overlap {overlap:.3f}, {inf['stream_chunks']} chunks")
+    ms_step = sum(p["call_ms"] for p in per)
+    res = base_result(args, w, nnz, nnz * N / (ms_step * 1e-3) / 1e9, ms_step)
+    kern_ms = float(np.mean([p["kernel_ms"] / p["chunks"] for p in per]))
+    chunk_nnz = per[0]["chunk_nnz"]
+    per_nnz = 12 + (N - 1) * R * 4
+    res["config"].update({"rank": R, "device_budget_bytes": budget, "placement": "pinned"})
+    res["roofline"] = {
+        "bound": "hbm", "achieved": chunk_nnz * per_nnz / (kern_ms * 1e-3) / 1e9,
+        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": chunk_nnz * per_nnz / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+        "kernel": f"k_mttkrp_win<32, float, {N}> per chunk", "bytes_per_nnz": per_nnz,
+        "avg_kernel_ms": kern_ms,
+        "note": "the step itself is bound by host-to-device copies (per_mode h2d_gbs)",
+    }
+    res["per_mode"] = per
+    res["build_s"] = build_s
+    res["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        res["cpu_baseline"] = cpu_oracle_rate(oracle, coords, vals, A, args.cpu_sample_nnz, modes)
+        rng = np.random.default_rng(7)
+        worst = 0.0
+        for n in modes:
+            o = blco.mttkrp_stream(T, n, F, out=outs[n], device_budget=budget)
+            rows = sampled_rows(rng, w.dims[n], 40)
+            M, S = oracle.mttkrp_rows_f32(coords, vals, A, n, rows, w.dims)
+            got = o[torch.from_numpy(rows.astype(np.int64)).to(dev)].cpu().numpy()
+            nz = S > 0
+            worst = max(worst, float((np.abs(got - M)[nz] / S[nz]).max()))
+        res["errors"] = {"fp32": {"max": worst}}
+        log(f"max normalised error {worst:.2e}")
+    return res
+
+
+def planted_values(torch, coords, G, sigma, seed, synth, chunk=8_000_000):
+    """x_k = sum_r prod_m G^(m)[i_m^k, r] + N(0, sigma^2), formed with plain torch CPU ops in fp64."""
+    nnz = len(coords[0])
+    out = np.empty(nnz, dtype=np.float32)
+    Gt = [torch.from_numpy(g) for g in G]
+    noise = synth.draw_normal_f64(nnz, sigma, seed, synth.S_NOISE)
+    for a in range(0, nnz, chunk):
+        b = min(nnz, a + chunk)
+        p = None
+        for m, g in enumerate(Gt):
+            rows = g[torch.from_numpy(coords[m][a:b].astype(np.int64))]
+            p = rows if p is None else p * rows
+        out[a:b] = (p.sum(dim=1).numpy() + noise[a:b]).astype(np.float32)
+    return out
+
+
+def leg_cpgrad(args, torch, blco, synth, w):
+    dev = torch.device("cuda:0")
+    timer = Timer(torch)
+    t0 = time.time()
+    coords, _ = synth.workload_tensor(w, nnz=args.nnz, log=log)
+    nnz = len(coords[0])
+    G = [synth.draw_u01_matrix(d, 8, w.seed, synth.S_TRUTH + m) for m, d in enumerate(w.dims)]
+    vals = planted_values(torch, coords, G, 0.01, w.seed, synth)
+    log(f"generated {nnz} non-zeros with planted values in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    T = blco.build(coords, vals, w.dims)
+    build_s = time.time() - t0
+    N = len(w.dims)
+    R = w.ranks[0]
+    scale = R ** (-1.0 / (2 * N))
+    A = [synth.draw_factor(d, R, w.seed, m, 0, scale) for m, d in enumerate(w.dims)]
+    P = [torch.from_numpy(a).to(dev).requires_grad_(True) for a in A]
+    out = {}
+    for storage in ("fp32", "bf16"):
+        def step(storage=storage):
+            for p in P:
+                p.grad = None
+            loss = blco.CPLoss.apply(T, storage, *P)
+            loss.backward()
+            return loss
+        ms = timer(step, args.steps, args.warmup)
+        loss = step()
+        torch.cuda.synchronize()
+        out[storage] = {"ms_per_step": ms, "gnnz_s": nnz / (ms * 1e-3) / 1e9,
+                        "loss": float(loss.detach())}
+        log(f"CP loss+gradient ({storage}): {ms:.2f} ms/step")
+    ms_step = out["fp32"]["ms_per_step"]
+    res = base_result(args, w, nnz, nnz / (ms_step * 1e-3) / 1e9, ms_step)
+    res["metric"] = "CP loss + gradient step Gnnz/s (forward sampled reconstruction + N MTTKRPs)"
+    Pd = [p.detach() for p in P]
+    loss_ms = timer(lambda: blco.sampled_loss(T, Pd), args.steps)
+    per_nnz = 12 + 4 + N * R * 4
+    res["config"].update({"rank": R, "model_rank": 8, "noise_sigma": 0.01})
+    res["roofline"] = {
+        "bound": "hbm", "achieved": nnz * per_nnz / (loss_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": nnz * per_nnz / (loss_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "traffic": None, "kernel": f"k_loss_tile<32, float, {N}> (sampled reconstruction)",
+        "bytes_per_nnz": per_nnz, "avg_kernel_ms": loss_ms,
+    }
+    res["per_storage"] = out
+    res["build_s"] = build_s
+    res["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        S = min(args.cpu_sample_nnz, nnz)
+        t0 = time.time()
+        oracle.cp_grad([c[:S] for c in coords], vals[:S], [a.astype(np.float64) for a in A],
+                       dims=w.dims)
+        dt = time.time() - t0
+        res["cpu_baseline"] = {"value": S / dt / 1e9, "unit": "Gnnz/s", "cores": 1,
+                               "kind": "oracle", "sample": f"loss + {N}-mode gradient over the "
+                               f"first {S} non-zeros, fp64, single thread, {dt:.1f}s"}
+        f_ref, _ = oracle.cp_loss(coords, vals, [a.astype(np.float64) for a in A])
+        res["errors"] = {"loss_rel_fp32": abs(out["fp32"]["loss"] - f_ref) / f_ref,
+                         "loss_rel_bf16_vs_fp64": abs(out["bf16"]["loss"] - f_ref) / f_ref}
+        log(f"oracle loss {f_ref:.6e}, gpu {out['fp32']['loss']:.6e}")
+    return res
 
 
 def main():
@@ -32,8 +387,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="zipf3")
+    ap.add_argument("--workload", default="zipf3",
+                    choices=["zipf3", "uniform3", "zipf4", "oom3", "cpgrad4", "small"])
     ap.add_argument("--nnz", type=int, default=None, help="shrink the workload (same recipe)")
+    ap.add_argument("--budget", type=int, default=None, help="device budget for oom3 (bytes)")
     ap.add_argument("--cpu-sample-nnz", type=int, default=4_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -48,167 +405,13 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench needs a GPU"
-    dev = torch.device("cuda:0")
     w = synth.WORKLOADS[args.workload]
-    R = w.ranks[0]
-    N = len(w.dims)
-    t0 = time.time()
-    coords, vals = synth.workload_tensor(w, nnz=args.nnz)
-    nnz = len(vals)
-    log(f"generated {nnz} non-zeros in {time.time() - t0:.1f}s")
-    t0 = time.time()
-    T = blco.build(coords, vals, w.dims)
-    build_s = time.time() - t0
-    inf = T.info()
-    log(f"built BLCO in {build_s:.2f}s: T={inf['total_bits']} bits, {inf['nblocks']} block(s)")
-    A = synth.workload_factors(w, R)
-    F32 = [torch.from_numpy(a).to(dev) for a in A]
-    BF16 = [blco.cast_bf16(f) for f in F32]
-    distinct = [int(np.count_nonzero(np.bincount(c, minlength=d))) for c, d in zip(coords, w.dims)]
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream()
-    outs = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in w.dims]
-
-    def step(F):
-        for n in range(N):
-            blco.mttkrp(T, n, F, out=outs[n])
-
-    # ---- timed region: K all-mode steps, fp32 factors
-    for _ in range(args.warmup):
-        step(F32)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step(F32)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    log(f"fp32 all-mode step {ms_step:.3f} ms")
-
-    def per_mode(F, acc):
-        """Average ms per call for each mode: full call, or the MTTKRP kernel alone (acc)."""
-        res = []
-        for n in range(N):
-            fn = (lambda: blco.mttkrp_acc(T, n, F, outs[n])) if acc else \
-                (lambda: blco.mttkrp(T, n, F, out=outs[n]))
-            fn()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(args.steps):
-                fn()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            res.append(e0.elapsed_time(e1) / args.steps)
-        return res
-
-    call_f32 = per_mode(F32, False)
-    kern_f32 = per_mode(F32, True)
-    call_bf16 = per_mode(BF16, False)
-    kern_bf16 = per_mode(BF16, True)
-    # bf16 all-mode step
-    for _ in range(args.warmup):
-        step(BF16)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step(BF16)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_step_bf16 = ev0.elapsed_time(ev1) / args.steps
-
-    # ---- roofline of the dominant kernel (the MTTKRP kernel, fp32 factors)
-    per_nnz = 12 + (N - 1) * R * 4          # key + value streamed, N-1 factor rows gathered
-    alg_bytes = nnz * per_nnz                # per launch (one mode)
-    avg_kernel_ms = float(np.mean(kern_f32))
-    achieved = alg_bytes / (avg_kernel_ms * 1e-3) / 1e9
-    compulsory = []
-    for n in range(N):
-        b = nnz * 12 + sum(distinct[m] * R * 4 for m in range(N) if m != n) + 2 * w.dims[n] * R * 4
-        compulsory.append(b)
-
-    # ---- CPU baseline (the oracle) and accuracy against it
-    cpu = None
-    errs = {}
-    if not args.no_cpu_baseline:
-        import oracle
-
-        S = min(args.cpu_sample_nnz, nnz)
-        cs = [c[:S] for c in coords]
-        vs = vals[:S]
-        Ad = [a.astype(np.float64) for a in A]
-        t0 = time.time()
-        for n in range(N):
-            oracle.mttkrp(cs, vs, Ad, n)
-        cpu_s = time.time() - t0
-        cpu = {"value": S * N / cpu_s / 1e9, "unit": "Gnnz/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {S} non-zeros of the workload, all {N} modes, fp64, "
-                         f"single thread, {cpu_s:.1f}s"}
-        log(f"cpu oracle: {cpu['value']:.4f} Gnnz/s over {S} non-zeros x {N} modes")
-        rng = np.random.default_rng(7)
-        Ab = [oracle.bf16_round(a).astype(np.float64) for a in A]
-        vd = vals.astype(np.float64)
-        for label, F, Aref in (("fp32", F32, Ad), ("bf16", BF16, Ab), ("bf16_vs_fp32", BF16, Ad)):
-            worst = 0.0
-            med = []
-            for n in range(N):
-                o = blco.mttkrp(T, n, F, out=outs[n])
-                rows = np.unique(np.concatenate([np.arange(8), rng.integers(0, w.dims[n], 120)])
-                                 ).astype(np.uint32)
-                M, Ssum = oracle.mttkrp_rows(coords, vd, Aref, n, rows, w.dims)
-                got = o[torch.from_numpy(rows.astype(np.int64)).to(dev)].cpu().numpy()
-                nz = Ssum > 0
-                e = np.abs(got.astype(np.float64) - M)[nz] / Ssum[nz]
-                worst = max(worst, float(e.max()))
-                med.append(float(np.median(e)))
-            errs[label] = {"max": worst, "median": float(np.median(med))}
-        log(f"errors: {errs}")
-
-    tot = nnz * N
-    res = {
-        "metric": "MTTKRP Gnnz/s per mode & % HBM peak; bf16 vs fp32 factors at stated rel error",
-        "value": tot / (ms_step * 1e-3) / 1e9,
-        "unit": "Gnnz/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{w.name}: {N}-mode {'x'.join(str(d) for d in w.dims)}, {nnz} distinct "
-                        f"non-zeros, per-mode {'/'.join(map(str, w.index_dist[0]))} indices, "
-                        f"U(0,1) values, rank {R} N(0,1) factors; all-mode MTTKRP from one BLCO copy",
-            "nnz": nnz, "dims": list(w.dims), "rank": R, "modes": N,
-            "key_bits": inf["total_bits"], "blocks": inf["nblocks"],
-        },
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_mttkrp_win<32, float, 3>" if os.environ.get("BLCO_KERNEL", "win") == "win" else os.environ.get("BLCO_KERNEL"),
-            "bytes_per_nnz": per_nnz,
-            "avg_kernel_ms": avg_kernel_ms,
-        },
-        "cpu_baseline": cpu,
-        "per_mode": {
-            "fp32_call_ms": call_f32, "fp32_kernel_ms": kern_f32,
-            "fp32_gnnz_s": [nnz / (x * 1e-3) / 1e9 for x in call_f32],
-            "bf16_call_ms": call_bf16, "bf16_kernel_ms": kern_bf16,
-            "bf16_gnnz_s": [nnz / (x * 1e-3) / 1e9 for x in call_bf16],
-            "compulsory_bytes": compulsory,
-            "compulsory_gbs_fp32": [b / (x * 1e-3) / 1e9 for b, x in zip(compulsory, kern_f32)],
-            "distinct_indices": distinct,
-        },
-        "bf16": {"ms_per_step": ms_step_bf16, "value": tot / (ms_step_bf16 * 1e-3) / 1e9,
-                 "unit": "Gnnz/s"},
-        "errors": errs,
-        "build_s": build_s,
-    }
+    if args.workload == "oom3":
+        res = leg_oom(args, torch, blco, synth, w)
+    elif args.workload == "cpgrad4":
+        res = leg_cpgrad(args, torch, blco, synth, w)
+    else:
+        res = leg_inmemory(args, torch, blco, synth, w)
     print(json.dumps(res), flush=True)
 
 

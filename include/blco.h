@@ -87,6 +87,9 @@ typedef struct {
   size_t stream_peak_bytes;  /* last blco_mttkrp_stream call: factors + out + staging + tables */
   int64_t stream_chunks;     /* last blco_mttkrp_stream call: chunks transferred */
   int64_t stream_chunk_nnz;  /* last blco_mttkrp_stream call: non-zeros per staging buffer */
+  double stream_copy_ms;     /* last streaming call: host-to-device copy time, summed over chunks */
+  double stream_kernel_ms;   /* last streaming call: MTTKRP kernel time, summed over chunks */
+  double stream_total_ms;    /* last streaming call: first copy start to last kernel end */
 } blco_info_t;
 
 /*
@@ -147,7 +150,9 @@ int blco_mttkrp_v(blco_tensor* t, int mode, const float* values, const void* con
  * computed in memory (the budget must still cover factors, out and tensor).
  * Errors: as blco_mttkrp, plus ENOMEM when the budget cannot hold two
  * staging buffers of one 64-non-zero tile each.  The staging buffers
- * are allocated on the first call and kept by the tensor.
+ * are allocated on the first call and kept by the tensor.  The copies and
+ * kernels of each chunk are bracketed by timing events; blco_info reports
+ * their busy times (and waits for the call to finish to do so).
  */
 int blco_mttkrp_stream(blco_tensor* t, int mode, const void* const* factors, int factor_dtype,
                        int rank, float* out, size_t device_budget_bytes, void* stream);
@@ -166,7 +171,8 @@ int blco_sampled_loss(blco_tensor* t, const void* const* factors, int factor_dty
 /* dst[i] = bf16(src[i]), round to nearest even (NaN stays NaN); device arrays. */
 int blco_cast_bf16(const float* src, uint16_t* dst, int64_t n, void* stream);
 
-/* Layout and sizes of a tensor. */
+/* Layout, sizes and last streaming call statistics of a tensor (waits for the
+   last streaming call to finish when it has not been measured yet). */
 int blco_info(const blco_tensor* t, blco_info_t* info);
 
 /*

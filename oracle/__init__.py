@@ -42,6 +42,8 @@ def lib():
         L.oracle_mttkrp.argtypes = [ctypes.c_int, p, i64, p, p, p, ctypes.c_int, ctypes.c_int, p, p]
         L.oracle_mttkrp_rows.argtypes = [ctypes.c_int, p, i64, p, p, p, ctypes.c_int, ctypes.c_int,
                                          i64, p, p, p]
+        L.oracle_mttkrp_rows_f32.argtypes = [ctypes.c_int, p, i64, p, p, p, ctypes.c_int,
+                                             ctypes.c_int, i64, p, p, p]
         L.oracle_cp_model.argtypes = [ctypes.c_int, i64, p, p, ctypes.c_int, p]
         L.oracle_cp_loss.argtypes = [ctypes.c_int, i64, p, p, p, ctypes.c_int, p]
         L.oracle_cp_loss.restype = ctypes.c_double
@@ -105,6 +107,22 @@ def mttkrp_rows(coords, vals, factors, mode, rows, dims):
     S = np.empty((len(rw), R), dtype=np.float64)
     lib().oracle_mttkrp_rows(N, d.ctypes.data, len(v), _ptrs(cs), v.ctypes.data, _ptrs(fs), R,
                              mode, len(rw), rw.ctypes.data, M.ctypes.data, S.ctypes.data)
+    return M, S
+
+
+def mttkrp_rows_f32(coords, vals, factors, mode, rows, dims):
+    """mttkrp_rows for fp32 values and factors (read and widened exactly, element by element)."""
+    N = len(coords)
+    R = int([f for f in factors if f is not None][0].shape[1])
+    cs = [_c(c, np.uint32) for c in coords]
+    fs = [_c(f, np.float32) if f is not None else np.zeros((1, R), np.float32) for f in factors]
+    v = _c(vals, np.float32)
+    d = _c(dims, np.uint64)
+    rw = _c(rows, np.uint32)
+    M = np.empty((len(rw), R), dtype=np.float64)
+    S = np.empty((len(rw), R), dtype=np.float64)
+    lib().oracle_mttkrp_rows_f32(N, d.ctypes.data, len(v), _ptrs(cs), v.ctypes.data, _ptrs(fs), R,
+                                 mode, len(rw), rw.ctypes.data, M.ctypes.data, S.ctypes.data)
     return M, S
 
 

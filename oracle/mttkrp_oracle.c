@@ -107,3 +107,32 @@ double oracle_cp_loss(int N, int64_t nnz, const uint32_t* const* coords, const d
   }
   return f;
 }
+
+/*
+ * oracle_mttkrp_rows with fp32 values and factors, each converted exactly to
+ * fp64 as it is read (same definition, same visiting order; no fp64 copies of
+ * large factor matrices are needed).
+ */
+void oracle_mttkrp_rows_f32(int N, const uint64_t* dims, int64_t nnz, const uint32_t* const* coords,
+                            const float* vals, const float* const* factors, int R, int mode,
+                            int64_t nrows, const uint32_t* rows, double* M_rows, double* S_rows) {
+  int64_t* slot = (int64_t*)malloc(sizeof(int64_t) * (size_t)dims[mode]);
+  for (uint64_t i = 0; i < dims[mode]; ++i) slot[i] = -1;
+  for (int64_t j = 0; j < nrows; ++j) slot[rows[j]] = j;
+  memset(M_rows, 0, sizeof(double) * (size_t)nrows * (size_t)R);
+  if (S_rows) memset(S_rows, 0, sizeof(double) * (size_t)nrows * (size_t)R);
+  for (int64_t k = 0; k < nnz; ++k) {
+    int64_t j = slot[coords[mode][k]];
+    if (j < 0) continue;
+    for (int r = 0; r < R; ++r) {
+      double p = (double)vals[k];
+      for (int m = 0; m < N; ++m) {
+        if (m == mode) continue;
+        p *= (double)factors[m][(size_t)coords[m][k] * (size_t)R + (size_t)r];
+      }
+      M_rows[(size_t)j * (size_t)R + (size_t)r] += p;
+      if (S_rows) S_rows[(size_t)j * (size_t)R + (size_t)r] += fabs(p);
+    }
+  }
+  free(slot);
+}

@@ -55,7 +55,8 @@ class _Info(ctypes.Structure):
                 ("nruns", ctypes.c_int64), ("placement", ctypes.c_int),
                 ("device_bytes", ctypes.c_size_t), ("host_bytes", ctypes.c_size_t),
                 ("stream_peak_bytes", ctypes.c_size_t), ("stream_chunks", ctypes.c_int64),
-                ("stream_chunk_nnz", ctypes.c_int64)]
+                ("stream_chunk_nnz", ctypes.c_int64), ("stream_copy_ms", ctypes.c_double),
+                ("stream_kernel_ms", ctypes.c_double), ("stream_total_ms", ctypes.c_double)]
 
 
 def library_path() -> str:
@@ -121,7 +122,8 @@ class BLCOTensor:
                     nblocks=inf.nblocks, nruns=inf.nruns, placement=inf.placement,
                     device_bytes=inf.device_bytes, host_bytes=inf.host_bytes,
                     stream_peak_bytes=inf.stream_peak_bytes, stream_chunks=inf.stream_chunks,
-                    stream_chunk_nnz=inf.stream_chunk_nnz)
+                    stream_chunk_nnz=inf.stream_chunk_nnz, stream_copy_ms=inf.stream_copy_ms,
+                    stream_kernel_ms=inf.stream_kernel_ms, stream_total_ms=inf.stream_total_ms)
 
     @property
     def nnz(self) -> int:

@@ -1206,6 +1206,10 @@ static void release_device(blco_tensor* t) {
       if (st.ev_free[i]) (void)hipEventSynchronize((hipEvent_t)st.ev_free[i]);
     }
   }
+  for (void* e : st.ev_t) {
+    (void)hipEventSynchronize((hipEvent_t)e);
+    (void)hipEventDestroy((hipEvent_t)e);
+  }
   for (int i = 0; i < 2; ++i) {
     if (st.d_keys[i]) (void)hipFree(st.d_keys[i]);
     if (st.d_vals[i]) (void)hipFree(st.d_vals[i]);
@@ -1391,23 +1395,38 @@ extern "C" int blco_mttkrp_stream(blco_tensor* t, int mode, const void* const* f
     st.cap_nnz = cap;
   }
   if ((rc = fill_zero(out, (int64_t)L.dims[mode] * rank, s))) return rc;
+  const int64_t nchunks = (t->nnz + cap - 1) / cap;
+  // the previous call's timing events must have fired before they are reused
+  for (size_t i = 0; i < st.ev_t.size(); ++i) HIPCHK(hipEventSynchronize((hipEvent_t)st.ev_t[i]));
+  while ((int64_t)st.ev_t.size() < 4 * nchunks) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    st.ev_t.push_back(e);
+  }
+  st.timed_chunks = 0;
   int64_t chunks = 0;
   for (int64_t lo = 0; lo < t->nnz; lo += cap, ++chunks) {
     const int b = (int)(chunks & 1);
     const int64_t cnt = std::min(cap, t->nnz - lo);
     hipStream_t cs = (hipStream_t)st.copy_stream;
+    hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(&st.ev_t[4 * chunks]);
     HIPCHK(hipStreamWaitEvent(cs, (hipEvent_t)st.ev_free[b], 0));
+    HIPCHK(hipEventRecord(ev[0], cs));
     HIPCHK(hipMemcpyAsync(st.d_keys[b], t->h_keys + lo, sizeof(uint64_t) * (size_t)cnt,
                           hipMemcpyHostToDevice, cs));
     HIPCHK(hipMemcpyAsync(st.d_vals[b], t->h_vals + lo, sizeof(float) * (size_t)cnt,
                           hipMemcpyHostToDevice, cs));
+    HIPCHK(hipEventRecord(ev[1], cs));
     HIPCHK(hipEventRecord((hipEvent_t)st.ev_ready[b], cs));
     HIPCHK(hipStreamWaitEvent(s, (hipEvent_t)st.ev_ready[b], 0));
+    HIPCHK(hipEventRecord(ev[2], s));
     if ((rc = launch_mttkrp(t, st.d_keys[b], st.d_vals[b], lo, cnt, mode, factors, factor_dtype,
                             rank, 1.0f, nullptr, out, s)))
       return rc;
+    HIPCHK(hipEventRecord(ev[3], s));
     HIPCHK(hipEventRecord((hipEvent_t)st.ev_free[b], s));
   }
+  st.timed_chunks = chunks;
   t->stream_peak_bytes = fixed + 2 * (size_t)cap * per_nnz;
   t->stream_chunks = chunks;
   return BLCO_OK;
@@ -1496,6 +1515,25 @@ extern "C" int blco_info(const blco_tensor* t, blco_info_t* info) {
   info->stream_peak_bytes = t->stream_peak_bytes;
   info->stream_chunks = t->stream_chunks;
   info->stream_chunk_nnz = t->st.cap_nnz;
+  const StreamState& st = t->st;
+  if (st.timed_chunks > 0) {
+    hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(const_cast<void**>(st.ev_t.data()));
+    const int64_t n = st.timed_chunks;
+    HIPCHK(hipEventSynchronize(ev[4 * (n - 1) + 3]));
+    double copy = 0.0, kern = 0.0;
+    for (int64_t c = 0; c < n; ++c) {
+      float a = 0.f, b = 0.f;
+      HIPCHK(hipEventElapsedTime(&a, ev[4 * c], ev[4 * c + 1]));
+      HIPCHK(hipEventElapsedTime(&b, ev[4 * c + 2], ev[4 * c + 3]));
+      copy += a;
+      kern += b;
+    }
+    float tot = 0.f;
+    HIPCHK(hipEventElapsedTime(&tot, ev[0], ev[4 * (n - 1) + 3]));
+    info->stream_copy_ms = copy;
+    info->stream_kernel_ms = kern;
+    info->stream_total_ms = tot;
+  }
   return BLCO_OK;
 }
 

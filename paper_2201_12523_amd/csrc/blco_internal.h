@@ -32,6 +32,10 @@ struct StreamState {
   uint64_t* d_keys[2] = {nullptr, nullptr};
   float* d_vals[2] = {nullptr, nullptr};
   int64_t cap_nnz = 0;             // non-zeros per staging buffer
+  // timing events of the last call: per chunk copy start/end (copy stream)
+  // and kernel start/end (caller's stream)
+  std::vector<void*> ev_t;         // 4 per chunk
+  int64_t timed_chunks = 0;
 };
 
 }  // namespace blco

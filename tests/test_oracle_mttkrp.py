@@ -184,3 +184,18 @@ def test_bf16_round_pins():
     y = oracle.bf16_round(r)
     assert np.all(np.abs(y - r) <= np.abs(r) * 2.0 ** -8)
     assert np.all(y.view(np.uint32) & 0xFFFF == 0)
+
+
+def test_rows_f32_variant_matches_fp64():
+    dims = (40, 30, 20, 5)
+    coords, vals = _rand_sparse(dims, 3000, seed=77)
+    vals32 = vals.astype(np.float32)
+    rng = np.random.default_rng(78)
+    A32 = [rng.standard_normal((d, 6)).astype(np.float32) for d in dims]
+    for n in range(4):
+        rows = np.unique(np.array([0, 3, dims[n] - 1], dtype=np.uint32))
+        M, S = oracle.mttkrp_rows(coords, vals32.astype(np.float64),
+                                  [a.astype(np.float64) for a in A32], n, rows, dims)
+        M2, S2 = oracle.mttkrp_rows_f32(coords, vals32, A32, n, rows, dims)
+        np.testing.assert_array_equal(M, M2)
+        np.testing.assert_array_equal(S, S2)
