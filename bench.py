@@ -382,7 +382,67 @@ def leg_cpgrad(args, torch, blco, synth, w):
     return res
 
 
+def summarize_pmc(fetch_csv, write_csv, copy_bytes, kernel="void k_mttkrp_win<32, float, 3>",
+                  out=TRAFFIC_FILE):
+    """Per-launch HBM bytes of the MTTKRP kernel from two rocprofv3 --pmc runs.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are averaged over the MTTKRP
+    dispatches, and each is scaled by the ratio of the known size of a plain
+    device-to-device copy to what the same counter read for that copy.
+    """
+    import csv
+
+    def per_kernel(path, counter):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            key = "mttkrp" if name.startswith(kernel + "(") else (
+                "copy" if "copyBuffer" in name else None)
+            if key is None:
+                continue
+            acc.setdefault(key, []).append(float(r["Counter_Value"]))
+        # the calibration copy is the largest copy dispatch
+        red = {"mttkrp": np.mean, "copy": np.max}
+        return ({k: float(red[k](v)) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()})
+
+    f, fn = per_kernel(fetch_csv, "FETCH_SIZE")
+    w, wn = per_kernel(write_csv, "WRITE_SIZE")
+    # the largest copy dispatch is the calibration copy
+    fscale = copy_bytes / (f["copy"] * 1024.0)
+    wscale = copy_bytes / (w["copy"] * 1024.0)
+    fetch_b = f["mttkrp"] * 1024.0 * fscale
+    write_b = w["mttkrp"] * 1024.0 * wscale
+    lines = [
+        "# HBM traffic of the MTTKRP kernel (k_mttkrp_win<32, float, 3>), 50M-non-zero",
+        "# 2^22 x 2^21 x 2^20 Zipf(1.1) workload, R = 32, fp32 factors, per launch (one mode).",
+        "# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two rocprofv3 --pmc runs of",
+        "#   python3 bench.py --workload zipf3 --steps 2 --warmup 0 --no-cpu-baseline "
+        f"--calibrate-copy-bytes {copy_bytes}",
+        "# each scaled by copy_bytes / (counter of the calibration copy), then summed.",
+        f"kernel_source_sha256_16: {kernel_source_hash()}",
+        f"mttkrp_dispatches: {fn.get('mttkrp', 0)}",
+        f"fetch_kib_per_dispatch: {f['mttkrp']:.1f}",
+        f"write_kib_per_dispatch: {w['mttkrp']:.1f}",
+        f"copy_bytes: {copy_bytes}",
+        f"copy_fetch_kib: {f['copy']:.1f}",
+        f"copy_write_kib: {w['copy']:.1f}",
+        f"fetch_scale: {fscale:.4f}",
+        f"write_scale: {wscale:.4f}",
+        f"hbm_fetch_bytes_per_launch: {fetch_b:.0f}",
+        f"hbm_write_bytes_per_launch: {write_b:.0f}",
+        f"hbm_bytes_per_launch: {fetch_b + write_b:.0f}",
+    ]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
+        summarize_pmc(sys.argv[2], sys.argv[3], int(sys.argv[4]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -393,6 +453,9 @@ def main():
     ap.add_argument("--budget", type=int, default=None, help="device budget for oom3 (bytes)")
     ap.add_argument("--cpu-sample-nnz", type=int, default=4_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-bytes", type=int, default=0,
+                    help="also run one plain device-to-device copy of this many bytes "
+                         "(the reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -405,6 +468,14 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.calibrate_copy_bytes:
+        n = args.calibrate_copy_bytes // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = synth.WORKLOADS[args.workload]
     if args.workload == "oom3":
         res = leg_oom(args, torch, blco, synth, w)
