@@ -381,17 +381,17 @@ __device__ __forceinline__ float ld_buf<uint16_t>(__amdgpu_buffer_rsrc_t r, uint
 // Every target therefore costs one global atomic per (window, rank).  On
 // MI355X same-address atomics serialise (about 32 ns each), so merging the
 // whole window bounds the atomic chains of frequent output rows.
-template <int LPN, typename FT, int N>
+template <int LPN, int RPL, typename FT, int N>
 __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   constexpr int G = kWin / LPN;                 // groups of LPN lanes
   constexpr int PPG = kWin / G;                 // sorted positions per group (= LPN)
-  constexpr int U = PPG < BLCO_WIN_U ? PPG : BLCO_WIN_U;
+  constexpr int U = PPG < (BLCO_WIN_U / RPL) ? PPG : (BLCO_WIN_U / RPL);
   constexpr int NF = N + 1;                     // record fields
   constexpr int NP = NF <= 4 ? 4 : ((NF + 1) / 2) * 2;
   constexpr int NS = NP > NF ? NP : NF;         // staging/record region, u32 per position
   __shared__ __align__(16) uint32_t s_rec[kWin * NS];  // records by grouped position
   __shared__ uint64_t s_end[kWin / 64];
-  __shared__ float s_head[kWin];
+  __shared__ float s_head[kWin * RPL];
 #if BLCO_WIN_BITONIC
   __shared__ uint64_t s_key[kWin];
 #else
@@ -488,7 +488,8 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   __syncthreads();
 #endif
 
-  // ---- computing: rank-wise walk of LPN sorted positions per group
+  // ---- computing: LPN lanes per group, RPL ranks per lane (lane j holds ranks
+  // j, j + LPN, ...), each group walking LPN consecutive grouped positions
   const int g = tid / LPN;
   const int rl = tid % LPN;
   const int p0 = g * PPG;
@@ -496,6 +497,7 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   const uint64_t gmask = PPG >= 64 ? ~0ULL : ((1ULL << PPG) - 1);
   const bool starts_before =
       p0 > 0 && p0 < nvalid && !((s_end[(p0 - 1) >> 6] >> ((p0 - 1) & 63)) & 1);
+  const bool can_carry = p0 + PPG <= nvalid;
   __amdgpu_buffer_rsrc_t rs[N];
 #pragma unroll
   for (int m = 0; m < N; ++m)
@@ -503,43 +505,58 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
                                               (int)kBufFlags);
   const float scale = term_scale(p);
   const int R = p.R;
-  for (int r0 = 0; r0 < R; r0 += LPN) {
-    const int r = r0 + rl;
-    const bool ract = r < R;
-    const uint32_t loff = (uint32_t)(ract ? r : 0) * (uint32_t)sizeof(FT);
-    float acc = 0.f, carry = 0.f;
+  for (int r0 = 0; r0 < R; r0 += LPN * RPL) {
+    bool ract[RPL];
+    uint32_t loff[RPL];
+    float acc[RPL], carry[RPL];
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+      const int r = r0 + rl + k * LPN;
+      ract[k] = r < R;
+      loff[k] = (uint32_t)(ract[k] ? r : 0) * (uint32_t)sizeof(FT);
+      acc[k] = 0.f;
+      carry[k] = 0.f;
+    }
     bool first = true, has_carry = false;
     for (int q0 = 0; q0 < PPG; q0 += U) {
-      float pr[U];
+      float pr[U][RPL];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t* e = &s_rec[(p0 + q0 + u) * NP];
-        float v = __uint_as_float(e[N]);
+        const float xv = __uint_as_float(e[N]);
 #pragma unroll
-        for (int m = 0; m < N; ++m)
-          if (m != p.mode) v *= ld_buf<FT>(rs[m], e[m] + loff);
-        pr[u] = v;
+        for (int k = 0; k < RPL; ++k) pr[u][k] = xv;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+          if (m == p.mode) continue;
+          const uint32_t base = e[m];
+#pragma unroll
+          for (int k = 0; k < RPL; ++k) pr[u][k] *= ld_buf<FT>(rs[m], base + loff[k]);
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int q = q0 + u;
-        const int pp = p0 + q;
-        if (pp < nvalid) {
-          acc += pr[u];
-          const bool seg_end = (endw >> q) & 1;
-          if (seg_end || q == PPG - 1) {
-            if (first && starts_before) {
-              s_head[tid] = acc;
-            } else if (seg_end) {
-              if (ract) unsafeAtomicAdd(p.out + (size_t)seg_target(s_rec, pp * NP, p.mode, N) * R + r,
-                                        acc * scale);
-            } else {
-              carry = acc;
-              has_carry = true;
-            }
-            acc = 0.f;
-            first = false;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) acc[k] += pr[u][k];
+        const bool seg_end = (endw >> q) & 1;
+        if (seg_end || (q == PPG - 1 && can_carry)) {
+          if (first && starts_before) {
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) s_head[tid * RPL + k] = acc[k];
+          } else if (seg_end) {
+            const size_t row = (size_t)seg_target(s_rec, (p0 + q) * NP, p.mode, N) * R;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k)
+              if (ract[k]) unsafeAtomicAdd(p.out + row + r0 + rl + k * LPN, acc[k] * scale);
+          } else {
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) carry[k] = acc[k];
+            has_carry = true;
           }
+#pragma unroll
+          for (int k = 0; k < RPL; ++k) acc[k] = 0.f;
+          first = false;
         }
       }
     }
@@ -548,12 +565,14 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
       // this group owns a segment that continues into the next groups
       for (int g2 = g + 1; g2 < G; ++g2) {
         const int q2 = g2 * PPG;
-        carry += s_head[g2 * LPN + rl];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) carry[k] += s_head[(g2 * LPN + rl) * RPL + k];
         if ((s_end[q2 >> 6] >> (q2 & 63)) & gmask) break;
       }
-      if (ract)
-        unsafeAtomicAdd(p.out + (size_t)seg_target(s_rec, (p0 + PPG - 1) * NP, p.mode, N) * R + r,
-                        carry * scale);
+      const size_t row = (size_t)seg_target(s_rec, (p0 + PPG - 1) * NP, p.mode, N) * R;
+#pragma unroll
+      for (int k = 0; k < RPL; ++k)
+        if (ract[k]) unsafeAtomicAdd(p.out + row + r0 + rl + k * LPN, carry[k] * scale);
     }
     __syncthreads();
   }
@@ -915,17 +934,17 @@ static KernelFn pick_tile(int N) {
   }
 }
 
-template <int LPN, typename FT>
+template <int LPN, int RPL, typename FT>
 static KernelFn pick_win(int N) {
   switch (N) {
-    case 1: return k_mttkrp_win<LPN, FT, 1>;
-    case 2: return k_mttkrp_win<LPN, FT, 2>;
-    case 3: return k_mttkrp_win<LPN, FT, 3>;
-    case 4: return k_mttkrp_win<LPN, FT, 4>;
-    case 5: return k_mttkrp_win<LPN, FT, 5>;
-    case 6: return k_mttkrp_win<LPN, FT, 6>;
-    case 7: return k_mttkrp_win<LPN, FT, 7>;
-    default: return k_mttkrp_win<LPN, FT, 8>;
+    case 1: return k_mttkrp_win<LPN, RPL, FT, 1>;
+    case 2: return k_mttkrp_win<LPN, RPL, FT, 2>;
+    case 3: return k_mttkrp_win<LPN, RPL, FT, 3>;
+    case 4: return k_mttkrp_win<LPN, RPL, FT, 4>;
+    case 5: return k_mttkrp_win<LPN, RPL, FT, 5>;
+    case 6: return k_mttkrp_win<LPN, RPL, FT, 6>;
+    case 7: return k_mttkrp_win<LPN, RPL, FT, 7>;
+    default: return k_mttkrp_win<LPN, RPL, FT, 8>;
   }
 }
 
@@ -988,16 +1007,18 @@ static KernelFn select_tile(int N, int R, int fdt) {
   return pick_tile<64, uint16_t>(N);
 }
 
+// window kernel shape: R <= 16: 16 lanes x 1 rank; R <= 32: 16 x 2; R <= 64:
+// 32 x 2; larger: 64 x 2 per pass over the rank
+template <typename FT>
+static KernelFn select_win_t(int N, int R) {
+  if (R <= 16) return pick_win<16, 1, FT>(N);
+  if (R <= 32) return pick_win<16, 2, FT>(N);
+  if (R <= 64) return pick_win<32, 2, FT>(N);
+  return pick_win<64, 2, FT>(N);
+}
+
 static KernelFn select_win(int N, int R, int fdt) {
-  int lpn = lanes_per_nnz(R);
-  if (fdt == BLCO_F32) {
-    if (lpn == 16) return pick_win<16, float>(N);
-    if (lpn == 32) return pick_win<32, float>(N);
-    return pick_win<64, float>(N);
-  }
-  if (lpn == 16) return pick_win<16, uint16_t>(N);
-  if (lpn == 32) return pick_win<32, uint16_t>(N);
-  return pick_win<64, uint16_t>(N);
+  return fdt == BLCO_F32 ? select_win_t<float>(N, R) : select_win_t<uint16_t>(N, R);
 }
 
 static KernelFn select_loss(int N, int R, int fdt) {
