@@ -104,6 +104,7 @@ def row_errors(oracle, blco, torch, T, coords, vals, A_ref, F, outs, dims, modes
         e = np.abs(got - M)[nz] / S[nz]
         worst = max(worst, float(e.max()) if e.size else 0.0)
         meds.append(float(np.median(e)) if e.size else 0.0)
+        log(f"  oracle rows, mode {n}: max normalised error {worst:.2e}")
     return {"max": worst, "median": float(np.median(meds))}
 
 

@@ -353,6 +353,11 @@ __device__ __forceinline__ uint32_t seg_target(const uint32_t* rec, int at, int 
 }
 constexpr uint32_t kBufFlags = 0x00020000u;  // raw buffer resource word 3 (gfx9 family)
 
+// Factor-row gathers.  Raw buffer loads with a 32-bit byte offset (row * row
+// bytes + rank offset) when every factor is below 4 GiB: no 64-bit address
+// arithmetic, and the descriptor's size bound drops stray offsets.  Larger
+// factors take 64-bit global addresses (BIG).  (Structured, index-scaled
+// buffer loads would cover both but measured 1.5-2x slower on gfx950.)
 template <typename FT>
 __device__ __forceinline__ float ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t off);
 template <>
@@ -381,7 +386,7 @@ __device__ __forceinline__ float ld_buf<uint16_t>(__amdgpu_buffer_rsrc_t r, uint
 // Every target therefore costs one global atomic per (window, rank).  On
 // MI355X same-address atomics serialise (about 32 ns each), so merging the
 // whole window bounds the atomic chains of frequent output rows.
-template <int LPN, int RPL, typename FT, int N>
+template <int LPN, int RPL, typename FT, int N, bool BIG>
 __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   constexpr int G = kWin / LPN;                 // groups of LPN lanes
   constexpr int PPG = kWin / G;                 // sorted positions per group (= LPN)
@@ -445,15 +450,13 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
                    (tid == nvalid - 1 || (s_key[tid + 1] >> kWinBits) != (sk >> kWinBits));
   const uint64_t em = __ballot(end);
   if (lane == 0) s_end[tid >> 6] = em;
-  // gather this sorted position's record from the staging area: field m holds
-  // the byte offset of factor row i_m (the target's row index for m = mode),
-  // field N the value
+  // gather this sorted position's record from the staging area (fields as below)
   const int src = (int)(sk & (kWin - 1));
   uint32_t rec[NF];
 #pragma unroll
   for (int m = 0; m < N; ++m) {
     const uint32_t cm = s_rec[m * kWin + src];
-    rec[m] = (m == p.mode) ? cm : cm * p.rowbytes;
+    rec[m] = (BIG || m == p.mode) ? cm : cm * p.rowbytes;
   }
   rec[N] = s_rec[N * kWin + src];
   __syncthreads();
@@ -472,11 +475,12 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   __syncthreads();
   block_exclusive_scan<kBuckets, kWin>(s_hist, tid, s_wsum);
   // record of this non-zero at its grouped position: field m holds the byte
-  // offset of factor row i_m (the target's row index for m = mode), field N
-  // the value; padding lanes keep their own (trailing) positions
+  // offset of factor row i_m (the row index itself for m = mode, or when BIG),
+  // field N the value; padding lanes keep their own (trailing) positions
   const int pos = valid ? (int)(s_hist[bkt] + rank) : tid;
 #pragma unroll
-  for (int m = 0; m < N; ++m) s_rec[pos * NP + m] = (m == p.mode) ? c[m] : c[m] * p.rowbytes;
+  for (int m = 0; m < N; ++m)
+    s_rec[pos * NP + m] = (BIG || m == p.mode) ? c[m] : c[m] * p.rowbytes;
   s_rec[pos * NP + N] = __float_as_uint(x);
   __syncthreads();
   {
@@ -529,9 +533,16 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
 #pragma unroll
         for (int m = 0; m < N; ++m) {
           if (m == p.mode) continue;
-          const uint32_t base = e[m];
+          const uint32_t f = e[m];
+          if constexpr (BIG) {
+            const FT* rowp = static_cast<const FT*>(p.A[m]) + (size_t)f * R;
 #pragma unroll
-          for (int k = 0; k < RPL; ++k) pr[u][k] *= ld_buf<FT>(rs[m], base + loff[k]);
+            for (int k = 0; k < RPL; ++k)
+              pr[u][k] *= ld_factor<FT>(rowp, (size_t)(loff[k] / sizeof(FT)));
+          } else {
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) pr[u][k] *= ld_buf<FT>(rs[m], f + loff[k]);
+          }
         }
       }
 #pragma unroll
@@ -934,17 +945,17 @@ static KernelFn pick_tile(int N) {
   }
 }
 
-template <int LPN, int RPL, typename FT>
+template <int LPN, int RPL, typename FT, bool BIG>
 static KernelFn pick_win(int N) {
   switch (N) {
-    case 1: return k_mttkrp_win<LPN, RPL, FT, 1>;
-    case 2: return k_mttkrp_win<LPN, RPL, FT, 2>;
-    case 3: return k_mttkrp_win<LPN, RPL, FT, 3>;
-    case 4: return k_mttkrp_win<LPN, RPL, FT, 4>;
-    case 5: return k_mttkrp_win<LPN, RPL, FT, 5>;
-    case 6: return k_mttkrp_win<LPN, RPL, FT, 6>;
-    case 7: return k_mttkrp_win<LPN, RPL, FT, 7>;
-    default: return k_mttkrp_win<LPN, RPL, FT, 8>;
+    case 1: return k_mttkrp_win<LPN, RPL, FT, 1, BIG>;
+    case 2: return k_mttkrp_win<LPN, RPL, FT, 2, BIG>;
+    case 3: return k_mttkrp_win<LPN, RPL, FT, 3, BIG>;
+    case 4: return k_mttkrp_win<LPN, RPL, FT, 4, BIG>;
+    case 5: return k_mttkrp_win<LPN, RPL, FT, 5, BIG>;
+    case 6: return k_mttkrp_win<LPN, RPL, FT, 6, BIG>;
+    case 7: return k_mttkrp_win<LPN, RPL, FT, 7, BIG>;
+    default: return k_mttkrp_win<LPN, RPL, FT, 8, BIG>;
   }
 }
 
@@ -1007,18 +1018,20 @@ static KernelFn select_tile(int N, int R, int fdt) {
   return pick_tile<64, uint16_t>(N);
 }
 
-// window kernel shape: R <= 16: 16 lanes x 1 rank; R <= 32: 16 x 2; R <= 64:
-// 32 x 2; larger: 64 x 2 per pass over the rank
-template <typename FT>
+// window kernel shape (lanes per non-zero x ranks per lane), chosen by measurement on
+// the Zipf workloads: R <= 16: 16 x 1; R <= 32: 16 x 2 (8 x 4 was 1.8x slower);
+// R <= 64: 16 x 4 (10% faster than 32 x 2); larger: 64 x 2 per pass over the rank
+template <typename FT, bool BIG>
 static KernelFn select_win_t(int N, int R) {
-  if (R <= 16) return pick_win<16, 1, FT>(N);
-  if (R <= 32) return pick_win<16, 2, FT>(N);
-  if (R <= 64) return pick_win<32, 2, FT>(N);
-  return pick_win<64, 2, FT>(N);
+  if (R <= 16) return pick_win<16, 1, FT, BIG>(N);
+  if (R <= 32) return pick_win<16, 2, FT, BIG>(N);
+  if (R <= 64) return pick_win<16, 4, FT, BIG>(N);
+  return pick_win<64, 2, FT, BIG>(N);
 }
 
-static KernelFn select_win(int N, int R, int fdt) {
-  return fdt == BLCO_F32 ? select_win_t<float>(N, R) : select_win_t<uint16_t>(N, R);
+static KernelFn select_win(int N, int R, int fdt, bool big) {
+  if (fdt == BLCO_F32) return big ? select_win_t<float, true>(N, R) : select_win_t<float, false>(N, R);
+  return big ? select_win_t<uint16_t, true>(N, R) : select_win_t<uint16_t, false>(N, R);
 }
 
 static KernelFn select_loss(int N, int R, int fdt) {
@@ -1140,14 +1153,14 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
   p.xcd_remap = g_xcd_remap;
   const size_t fsz = factor_elem_bytes(fdt);
   p.rowbytes = (uint32_t)((size_t)rank * fsz);
-  bool fits32 = (size_t)rank * fsz < (1ULL << 31);
+  // factors below 4 GiB are gathered with 32-bit byte offsets, larger ones
+  // with 64-bit addresses
+  bool big = (size_t)rank * fsz >= (1ULL << 31);
   for (int m = 0; m < t->lay.N; ++m) {
     const size_t bytes = (size_t)t->lay.dims[m] * rank * fsz;
     p.abytes[m] = (uint32_t)std::min<size_t>(bytes, 0xFFFFFFFFull);
-    if (m != mode && bytes > 0xFFFFFFFFull) fits32 = false;
+    if (m != mode && bytes > 0xFFFFFFFFull) big = true;
   }
-  // the window kernel addresses factor rows with 32-bit byte offsets
-  if (var == kVarWin && !fits32) var = kVarTile;
   if (var == kVarNaive) {
     int64_t threads = n * (int64_t)rank;
     int64_t blocks = (threads + 255) / 256;
@@ -1190,7 +1203,7 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
   } else if (var == kVarWin) {
     int64_t blocks = (n + kWin - 1) / kWin;
     p.wide = t->lay.dims[mode] > (1ULL << (32 - kWinBits)) ? 1 : 0;
-    KernelFn f = select_win(t->lay.N, rank, fdt);
+    KernelFn f = select_win(t->lay.N, rank, fdt, big);
     hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(kWin), 0, s, p);
   } else {
     int64_t tiles = (n + 63) / 64;
