@@ -347,9 +347,10 @@ __device__ __forceinline__ void block_exclusive_scan(uint32_t* a, int tid, uint3
   __syncthreads();
 }
 
-// target row of a record (field `mode` of the record at LDS offset `at`)
+// target row of a record (field N - 1 of the record at LDS offset `at`)
 __device__ __forceinline__ uint32_t seg_target(const uint32_t* rec, int at, int mode, int N) {
-  return rec[at + mode];
+  (void)mode;
+  return rec[at + N - 1];
 }
 constexpr uint32_t kBufFlags = 0x00020000u;  // raw buffer resource word 3 (gfx9 family)
 
@@ -454,10 +455,11 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   const int src = (int)(sk & (kWin - 1));
   uint32_t rec[NF];
 #pragma unroll
-  for (int m = 0; m < N; ++m) {
-    const uint32_t cm = s_rec[m * kWin + src];
-    rec[m] = (BIG || m == p.mode) ? cm : cm * p.rowbytes;
+  for (int j = 0; j + 1 < N; ++j) {
+    const uint32_t cj = s_rec[((j < p.mode) ? j : j + 1) * kWin + src];
+    rec[j] = BIG ? cj : cj * p.rowbytes;
   }
+  rec[N - 1] = s_rec[p.mode * kWin + src];
   rec[N] = s_rec[N * kWin + src];
   __syncthreads();
 #pragma unroll
@@ -474,18 +476,22 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   if (valid) rank = atomicAdd(&s_hist[bkt], 1u);
   __syncthreads();
   block_exclusive_scan<kBuckets, kWin>(s_hist, tid, s_wsum);
-  // record of this non-zero at its grouped position: field m holds the byte
-  // offset of factor row i_m (the row index itself for m = mode, or when BIG),
-  // field N the value; padding lanes keep their own (trailing) positions
+  // record of this non-zero at its grouped position: fields 0..N-2 hold the byte
+  // offsets (row indices when BIG) of the factor rows of the other modes in
+  // ascending mode order, field N-1 the target row, field N the value; padding
+  // lanes keep their own (trailing) positions
   const int pos = valid ? (int)(s_hist[bkt] + rank) : tid;
 #pragma unroll
-  for (int m = 0; m < N; ++m)
-    s_rec[pos * NP + m] = (BIG || m == p.mode) ? c[m] : c[m] * p.rowbytes;
+  for (int j = 0; j + 1 < N; ++j) {
+    const uint32_t cj = (j < p.mode) ? c[j] : c[j + 1];
+    s_rec[pos * NP + j] = BIG ? cj : cj * p.rowbytes;
+  }
+  s_rec[pos * NP + N - 1] = tgt;
   s_rec[pos * NP + N] = __float_as_uint(x);
   __syncthreads();
   {
-    const uint32_t t0 = s_rec[tid * NP + p.mode];
-    const bool end = (tid < nvalid) && (tid == nvalid - 1 || s_rec[(tid + 1) * NP + p.mode] != t0);
+    const uint32_t t0 = s_rec[tid * NP + N - 1];
+    const bool end = (tid < nvalid) && (tid == nvalid - 1 || s_rec[(tid + 1) * NP + N - 1] != t0);
     const uint64_t em = __ballot(end);
     if (lane == 0) s_end[tid >> 6] = em;
   }
@@ -502,11 +508,16 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   const bool starts_before =
       p0 > 0 && p0 < nvalid && !((s_end[(p0 - 1) >> 6] >> ((p0 - 1) & 63)) & 1);
   const bool can_carry = p0 + PPG <= nvalid;
-  __amdgpu_buffer_rsrc_t rs[N];
+  constexpr int NO = N > 1 ? N - 1 : 1;          // other modes
+  __amdgpu_buffer_rsrc_t rs[NO];
+  const void* ap[NO];
 #pragma unroll
-  for (int m = 0; m < N; ++m)
-    rs[m] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.A[m]), 0, (int)p.abytes[m],
+  for (int j = 0; j + 1 < N; ++j) {
+    const int m = (j < p.mode) ? j : j + 1;
+    ap[j] = p.A[m];
+    rs[j] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.A[m]), 0, (int)p.abytes[m],
                                               (int)kBufFlags);
+  }
   const float scale = term_scale(p);
   const int R = p.R;
   for (int r0 = 0; r0 < R; r0 += LPN * RPL) {
@@ -531,17 +542,16 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
 #pragma unroll
         for (int k = 0; k < RPL; ++k) pr[u][k] = xv;
 #pragma unroll
-        for (int m = 0; m < N; ++m) {
-          if (m == p.mode) continue;
-          const uint32_t f = e[m];
+        for (int j = 0; j + 1 < N; ++j) {
+          const uint32_t f = e[j];
           if constexpr (BIG) {
-            const FT* rowp = static_cast<const FT*>(p.A[m]) + (size_t)f * R;
+            const FT* rowp = static_cast<const FT*>(ap[j]) + (size_t)f * R;
 #pragma unroll
             for (int k = 0; k < RPL; ++k)
               pr[u][k] *= ld_factor<FT>(rowp, (size_t)(loff[k] / sizeof(FT)));
           } else {
 #pragma unroll
-            for (int k = 0; k < RPL; ++k) pr[u][k] *= ld_buf<FT>(rs[m], f + loff[k]);
+            for (int k = 0; k < RPL; ++k) pr[u][k] *= ld_buf<FT>(rs[j], f + loff[k]);
           }
         }
       }
