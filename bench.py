@@ -197,7 +197,7 @@ def leg_inmemory(args, torch, blco, synth, w):
     res["roofline"] = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-        "kernel": f"k_mttkrp_win<{32 if R <= 32 else 64}, float, {N}>",
+        "kernel": win_kernel_name(R, N),
         "bytes_per_nnz": per_nnz, "avg_kernel_ms": avg_kernel_ms,
         "compulsory_bytes_per_launch": compulsory,
     }
@@ -277,7 +277,7 @@ def leg_oom(args, torch, blco, synth, w):
         "bound": "hbm", "achieved": chunk_nnz * per_nnz / (kern_ms * 1e-3) / 1e9,
         "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": chunk_nnz * per_nnz / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-        "kernel": f"k_mttkrp_win<32, float, {N}> per chunk", "bytes_per_nnz": per_nnz,
+        "kernel": win_kernel_name(R, N) + " per chunk", "bytes_per_nnz": per_nnz,
         "avg_kernel_ms": kern_ms,
         "note": "the step itself is bound by host-to-device copies (per_mode h2d_gbs)",
     }
@@ -383,8 +383,13 @@ def leg_cpgrad(args, torch, blco, synth, w):
     return res
 
 
-def summarize_pmc(fetch_csv, write_csv, copy_bytes, kernel="void k_mttkrp_win<32, float, 3>",
-                  out=TRAFFIC_FILE):
+def win_kernel_name(R, N, ft="float", big=False):
+    """Template name of the window MTTKRP kernel the library launches for rank R."""
+    lpn, rpl = (16, 1) if R <= 16 else (16, 2) if R <= 32 else (16, 4) if R <= 64 else (64, 2)
+    return f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {'true' if big else 'false'}>"
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_bytes, kernel=None, out=TRAFFIC_FILE):
     """Per-launch HBM bytes of the MTTKRP kernel from two rocprofv3 --pmc runs.
 
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are averaged over the MTTKRP
@@ -392,6 +397,8 @@ def summarize_pmc(fetch_csv, write_csv, copy_bytes, kernel="void k_mttkrp_win<32
     device-to-device copy to what the same counter read for that copy.
     """
     import csv
+
+    kernel = kernel or "void " + win_kernel_name(32, 3)
 
     def per_kernel(path, counter):
         acc = {}
@@ -416,7 +423,7 @@ def summarize_pmc(fetch_csv, write_csv, copy_bytes, kernel="void k_mttkrp_win<32
     fetch_b = f["mttkrp"] * 1024.0 * fscale
     write_b = w["mttkrp"] * 1024.0 * wscale
     lines = [
-        "# HBM traffic of the MTTKRP kernel (k_mttkrp_win<32, float, 3>), 50M-non-zero",
+        f"# HBM traffic of the MTTKRP kernel ({kernel[5:]}), 50M-non-zero",
         "# 2^22 x 2^21 x 2^20 Zipf(1.1) workload, R = 32, fp32 factors, per launch (one mode).",
         "# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two rocprofv3 --pmc runs of",
         "#   python3 bench.py --workload zipf3 --steps 2 --warmup 0 --no-cpu-baseline "
