@@ -158,6 +158,20 @@ int blco_mttkrp_stream(blco_tensor* t, int mode, const void* const* factors, int
                        int rank, float* out, size_t device_budget_bytes, void* stream);
 
 /*
+ * Out-of-memory MTTKRP of several modes in one pass over the non-zeros: each
+ * chunk is copied to the device once and, while resident, the MTTKRP of every
+ * mode m with outs[m] != NULL is computed into outs[m] (device, I_m x R fp32,
+ * overwritten; outputs must not overlap each other or a factor).  `outs` is a
+ * host array of N pointers.  The budget covers the factors the selected modes
+ * read, all selected outputs, the tensor's tables and the two staging buffers.
+ * With N modes this moves the non-zeros over the host link once instead of N
+ * times (the per-mode form is the paper's, Section 4.2).  Errors: as
+ * blco_mttkrp_stream, EINVAL when no output is given or outputs overlap.
+ */
+int blco_mttkrp_stream_all(blco_tensor* t, const void* const* factors, int factor_dtype, int rank,
+                           float* const* outs, size_t device_budget_bytes, void* stream);
+
+/*
  * Sparse CP fit loss at the non-zeros (model of Section 2.2):
  *   xhat_k = sum_r prod_{m} A^(m)[i_m^k, r],  e_k = x_k - xhat_k,
  *   *loss = 1/2 sum_k e_k^2

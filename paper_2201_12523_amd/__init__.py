@@ -17,7 +17,8 @@ import os
 import numpy as np
 import torch  # noqa: F401  (must precede loading libblco.so)
 
-__all__ = ["BLCOTensor", "build", "mttkrp", "mttkrp_acc", "mttkrp_v", "mttkrp_stream", "sampled_loss",
+__all__ = ["BLCOTensor", "build", "mttkrp", "mttkrp_acc", "mttkrp_v", "mttkrp_stream",
+           "mttkrp_stream_all", "sampled_loss",
            "cast_bf16", "CPLoss", "BLCOError", "lib", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,6 +31,7 @@ PLACEMENTS = {"device": 0, "pinned": 1, "host": 2}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: "EUNSUPPORTED"}
 
 EXPORTED = ["blco_build", "blco_mttkrp", "blco_mttkrp_acc", "blco_mttkrp_v", "blco_mttkrp_stream",
+            "blco_mttkrp_stream_all",
             "blco_sampled_loss", "blco_cast_bf16", "blco_info", "blco_export", "blco_free",
             "blco_last_error"]
 
@@ -76,6 +78,7 @@ def lib():
         L.blco_mttkrp_acc.argtypes = [p, i32, p, i32, i32, p, p]
         L.blco_mttkrp_v.argtypes = [p, i32, p, p, i32, i32, p, ctypes.c_double, p, p]
         L.blco_mttkrp_stream.argtypes = [p, i32, p, i32, i32, p, ctypes.c_size_t, p]
+        L.blco_mttkrp_stream_all.argtypes = [p, p, i32, i32, p, ctypes.c_size_t, p]
         L.blco_sampled_loss.argtypes = [p, p, i32, i32, p, p, p]
         L.blco_cast_bf16.argtypes = [p, p, i64, p]
         L.blco_info.argtypes = [p, ctypes.POINTER(_Info)]
@@ -255,6 +258,24 @@ def mttkrp_stream(t, mode, factors, out=None, device_budget=8_000_000_000, strea
     _check(lib().blco_mttkrp_stream(t.handle, mode, arr, dt, R, out.data_ptr(),
                                     int(device_budget), _stream(stream)))
     return out
+
+
+def mttkrp_stream_all(t, factors, outs=None, device_budget=8_000_000_000, modes=None,
+                      stream=None):
+    """MTTKRP of several modes (default: all) in one streamed pass over a pinned tensor."""
+    arr, dt, R, _keep = _factor_args(t, factors, None)
+    dev = _device_of(factors)
+    modes = list(range(len(t.dims))) if modes is None else list(modes)
+    if outs is None:
+        outs = [None] * len(t.dims)
+    outs = list(outs)
+    for m in modes:
+        outs[m] = _out(t, m, R, outs[m], dev)
+    ptrs = (ctypes.c_void_p * len(t.dims))(*[outs[m].data_ptr() if m in modes else None
+                                               for m in range(len(t.dims))])
+    _check(lib().blco_mttkrp_stream_all(t.handle, arr, dt, R, ptrs, int(device_budget),
+                                        _stream(stream)))
+    return [outs[m] if m in modes else None for m in range(len(t.dims))]
 
 
 def sampled_loss(t, factors, residual=None, loss=None, stream=None):

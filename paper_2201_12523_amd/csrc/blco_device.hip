@@ -1377,31 +1377,50 @@ extern "C" int blco_mttkrp_acc(blco_tensor* t, int mode, const void* const* fact
                        1.0f, nullptr, out, (hipStream_t)stream);
 }
 
-extern "C" int blco_mttkrp_stream(blco_tensor* t, int mode, const void* const* factors,
-                                  int factor_dtype, int rank, float* out,
-                                  size_t device_budget_bytes, void* stream) {
-  clear_error();
-  int rc = check_factor_args(t, mode, factors, factor_dtype, rank, out, false);
-  if (rc) return rc;
+// Stream the pinned non-zeros once through two reused staging buffers and,
+// for every chunk, run the MTTKRP of each selected mode (outs[m] != NULL) while
+// the chunk is resident.  Device bytes: factors read + selected outputs +
+// tensor tables + two staging buffers <= budget.
+static int stream_modes(blco_tensor* t, const void* const* factors, int factor_dtype, int rank,
+                        float* const* outs, size_t device_budget_bytes, hipStream_t s) {
   const Layout& L = t->lay;
-  size_t fixed = (size_t)L.dims[mode] * rank * sizeof(float);
+  bool need[BLCO_MAX_MODES] = {};
+  int nsel = 0;
   for (int m = 0; m < L.N; ++m)
-    if (m != mode) fixed += (size_t)L.dims[m] * rank * factor_elem_bytes(factor_dtype);
-  fixed += t->device_bytes;
+    if (outs[m]) {
+      ++nsel;
+      for (int j = 0; j < L.N; ++j)
+        if (j != m) need[j] = true;
+    }
+  if (nsel == 0) return set_error(BLCO_EINVAL, "no output given");
+  size_t fixed = t->device_bytes;
+  for (int m = 0; m < L.N; ++m) {
+    if (outs[m]) fixed += (size_t)L.dims[m] * rank * sizeof(float);
+    if (need[m]) fixed += (size_t)L.dims[m] * rank * factor_elem_bytes(factor_dtype);
+  }
+  int rc;
   if (t->placement == BLCO_PLACE_DEVICE) {
     if (fixed > device_budget_bytes)
-      return set_error(BLCO_ENOMEM, "budget %zu below factors + out + tensor = %zu",
+      return set_error(BLCO_ENOMEM, "budget %zu below factors + outputs + tensor = %zu",
                        device_budget_bytes, fixed);
+    for (int m = 0; m < L.N; ++m) {
+      if (!outs[m]) continue;
+      if ((rc = fill_zero(outs[m], (int64_t)L.dims[m] * rank, s))) return rc;
+      if ((rc = launch_mttkrp(t, t->d_keys, t->d_vals, 0, t->nnz, m, factors, factor_dtype, rank,
+                              1.0f, nullptr, outs[m], s)))
+        return rc;
+    }
     t->stream_peak_bytes = fixed;
     t->stream_chunks = 0;
-    return blco_mttkrp(t, mode, factors, factor_dtype, rank, out, stream);
+    t->st.timed_chunks = 0;
+    return BLCO_OK;
   }
   if (t->placement != BLCO_PLACE_PINNED)
     return set_error(BLCO_EINVAL, "streaming needs a tensor in pinned host memory");
   const size_t per_nnz = sizeof(uint64_t) + sizeof(float);
   if (device_budget_bytes < fixed + 2 * 64 * per_nnz)
-    return set_error(BLCO_ENOMEM, "budget %zu cannot hold factors + out + tables (%zu) and two "
-                                  "staging buffers", device_budget_bytes, fixed);
+    return set_error(BLCO_ENOMEM, "budget %zu cannot hold factors + outputs + tables (%zu) and "
+                                  "two staging buffers", device_budget_bytes, fixed);
   int64_t cap = (int64_t)((device_budget_bytes - fixed) / 2 / per_nnz);
   int64_t blk_cap = ((t->max_block_nnz + 63) / 64) * 64;
   cap = std::min(cap, blk_cap);
@@ -1409,7 +1428,6 @@ extern "C" int blco_mttkrp_stream(blco_tensor* t, int mode, const void* const* f
   cap = (cap / 64) * 64;
   if (cap < 64) cap = 64;
   StreamState& st = t->st;
-  hipStream_t s = (hipStream_t)stream;
   if (!st.copy_stream) {
     hipStream_t cs;
     HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -1438,7 +1456,8 @@ extern "C" int blco_mttkrp_stream(blco_tensor* t, int mode, const void* const* f
     }
     st.cap_nnz = cap;
   }
-  if ((rc = fill_zero(out, (int64_t)L.dims[mode] * rank, s))) return rc;
+  for (int m = 0; m < L.N; ++m)
+    if (outs[m] && (rc = fill_zero(outs[m], (int64_t)L.dims[m] * rank, s))) return rc;
   const int64_t nchunks = (t->nnz + cap - 1) / cap;
   // the previous call's timing events must have fired before they are reused
   for (size_t i = 0; i < st.ev_t.size(); ++i) HIPCHK(hipEventSynchronize((hipEvent_t)st.ev_t[i]));
@@ -1464,9 +1483,12 @@ extern "C" int blco_mttkrp_stream(blco_tensor* t, int mode, const void* const* f
     HIPCHK(hipEventRecord((hipEvent_t)st.ev_ready[b], cs));
     HIPCHK(hipStreamWaitEvent(s, (hipEvent_t)st.ev_ready[b], 0));
     HIPCHK(hipEventRecord(ev[2], s));
-    if ((rc = launch_mttkrp(t, st.d_keys[b], st.d_vals[b], lo, cnt, mode, factors, factor_dtype,
-                            rank, 1.0f, nullptr, out, s)))
-      return rc;
+    for (int m = 0; m < L.N; ++m) {
+      if (!outs[m]) continue;
+      if ((rc = launch_mttkrp(t, st.d_keys[b], st.d_vals[b], lo, cnt, m, factors, factor_dtype,
+                              rank, 1.0f, nullptr, outs[m], s)))
+        return rc;
+    }
     HIPCHK(hipEventRecord(ev[3], s));
     HIPCHK(hipEventRecord((hipEvent_t)st.ev_free[b], s));
   }
@@ -1474,6 +1496,47 @@ extern "C" int blco_mttkrp_stream(blco_tensor* t, int mode, const void* const* f
   t->stream_peak_bytes = fixed + 2 * (size_t)cap * per_nnz;
   t->stream_chunks = chunks;
   return BLCO_OK;
+}
+
+extern "C" int blco_mttkrp_stream(blco_tensor* t, int mode, const void* const* factors,
+                                  int factor_dtype, int rank, float* out,
+                                  size_t device_budget_bytes, void* stream) {
+  clear_error();
+  int rc = check_factor_args(t, mode, factors, factor_dtype, rank, out, false);
+  if (rc) return rc;
+  float* outs[BLCO_MAX_MODES] = {};
+  outs[mode] = out;
+  return stream_modes(t, factors, factor_dtype, rank, outs, device_budget_bytes,
+                      (hipStream_t)stream);
+}
+
+extern "C" int blco_mttkrp_stream_all(blco_tensor* t, const void* const* factors,
+                                      int factor_dtype, int rank, float* const* outs,
+                                      size_t device_budget_bytes, void* stream) {
+  clear_error();
+  if (!t) return set_error(BLCO_EINVAL, "tensor is NULL");
+  if (!outs) return set_error(BLCO_EINVAL, "outs is NULL");
+  float* o[BLCO_MAX_MODES] = {};
+  int first = -1;
+  for (int m = 0; m < t->lay.N; ++m) {
+    o[m] = outs[m];
+    if (o[m] && first < 0) first = m;
+  }
+  if (first < 0) return set_error(BLCO_EINVAL, "no output given");
+  for (int m = 0; m < t->lay.N; ++m) {
+    if (!o[m]) continue;
+    int rc = check_factor_args(t, m, factors, factor_dtype, rank, o[m], false);
+    if (rc) return rc;
+    for (int j = 0; j < t->lay.N; ++j) {
+      if (j == m || !o[j]) continue;
+      const float* a = o[m];
+      const float* b = o[j];
+      const size_t na = (size_t)t->lay.dims[m] * rank, nb = (size_t)t->lay.dims[j] * rank;
+      if (a < b + nb && b < a + na) return set_error(BLCO_EINVAL, "outs[%d] overlaps outs[%d]", m, j);
+    }
+  }
+  return stream_modes(t, factors, factor_dtype, rank, o, device_budget_bytes,
+                      (hipStream_t)stream);
 }
 
 extern "C" int blco_sampled_loss(blco_tensor* t, const void* const* factors, int factor_dtype,

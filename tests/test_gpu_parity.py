@@ -368,3 +368,34 @@ def test_zipf3_full_size_sampled_rows():
             inner.append(float((out.double() * Fd.double()).sum()))
             inner_abs.append(float((out.double().abs() * Fd.double().abs()).sum()))
         assert max(inner) - min(inner) <= 1e-5 * max(inner_abs), (inner, inner_abs)
+
+
+@pytest.mark.parametrize("placement", ["pinned", "device"])
+def test_stream_all_modes_one_pass(placement):
+    rng = np.random.default_rng(77)
+    dims = (300, 200, 100, 7)
+    nnz = 20_000
+    coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
+    vals = rng.random(nnz).astype(np.float32)
+    R = 16
+    A = [rng.standard_normal((d, R)).astype(np.float32) for d in dims]
+    F = _dev_factors(A)
+    t = blco.build(coords, vals, dims, placement=placement)
+    fixed = sum(d * R * 4 * 2 for d in dims) + t.info()["device_bytes"]
+    budget = fixed + 2 * 1000 * 12
+    outs = blco.mttkrp_stream_all(t, F, device_budget=budget)
+    torch.cuda.synchronize()
+    inf = t.info()
+    if placement == "pinned":
+        assert inf["stream_chunks"] == -(-nnz // inf["stream_chunk_nnz"]) and inf["stream_chunks"] > 10
+        assert inf["stream_peak_bytes"] <= budget
+    for n in range(4):
+        M, S = oracle.mttkrp(coords, vals, A, n)
+        check_entries(outs[n].cpu().numpy(), M, S, label=f"stream_all {placement} mode {n}")
+    # a subset of modes, the others untouched
+    keep = torch.full((dims[1], R), 5.0, device=DEV)
+    outs2 = blco.mttkrp_stream_all(t, F, outs=[None, keep, None, None], modes=[1, 3],
+                                   device_budget=budget)
+    M, S = oracle.mttkrp(coords, vals, A, 1)
+    check_entries(outs2[1].cpu().numpy(), M, S, label="stream_all subset")
+    assert outs2[0] is None and outs2[2] is None

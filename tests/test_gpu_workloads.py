@@ -140,3 +140,15 @@ def test_oom3_recipe_streamed():
         assert inf["stream_chunks"] >= 8 and inf["stream_peak_bytes"] <= budget
         check_rows(out, coords, vals, A, n, w.dims, rows_for(rng, w.dims[n]), 1e-5,
                    f"oom3 streamed mode {n}")
+    # every mode in one pass over the non-zeros
+    fixed = sum(int(np.prod(a.shape)) * 4 * 2 for a in A) + t.info()["device_bytes"]
+    budget = fixed + 2 * (3 << 20) * 12
+    outs = blco.mttkrp_stream_all(t, F, device_budget=budget)
+    torch.cuda.synchronize()
+    inf = t.info()
+    say(f"oom3 all modes: {inf['stream_chunks']} chunks, copy {inf['stream_copy_ms']:.1f} ms, "
+        f"kernels {inf['stream_kernel_ms']:.1f} ms, span {inf['stream_total_ms']:.1f} ms")
+    assert inf["stream_chunks"] >= 8 and inf["stream_peak_bytes"] <= budget
+    for n in range(3):
+        check_rows(outs[n], coords, vals, A, n, w.dims, rows_for(rng, w.dims[n]), 1e-5,
+                   f"oom3 one-pass mode {n}")
