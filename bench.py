@@ -15,7 +15,10 @@ Other legs (``--workload``):
            streamed under an 8 GB device budget; copy/compute overlap reported;
   cpgrad4  sparse CP loss + gradient step, 4-mode 2^20 x 2^18 x 2^16 x 2^12,
            80M non-zeros holding a planted rank-8 model plus noise, R = 32;
-  uniform3 the zipf3 shape with uniform indices.
+  uniform3 the zipf3 shape with uniform indices;
+  short4   4-mode 2^21 x 2^17 x 24 x 168, 50M non-zeros, R = 32: the two short
+           modes take hierarchical conflict resolution (Section 5.3 heuristic),
+           and the register-based mechanism is timed beside it on those modes.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -175,15 +178,26 @@ def leg_inmemory(args, torch, blco, synth, w):
             kern = [timer(lambda n=n: blco.mttkrp_acc(T, n, F, outs[n]), args.steps) for n in modes]
             sf = 4 if tag == "fp32" else 2
             per_nnz = 12 + (N - 1) * R * sf
+            mech = [T.resolution(n, R) for n in modes]
+            alt = {}
+            for n in modes:
+                if mech[n] == "hierarchical":
+                    # the other mechanism on the same mode, for the Section 5.3 comparison
+                    T.set_resolution("register")
+                    alt[n] = timer(lambda n=n: blco.mttkrp_acc(T, n, F, outs[n]), args.steps)
+                    T.set_resolution("auto")
             results[f"R{R}_{tag}"] = {
                 "ms_per_step": ms_step, "gnnz_s": nnz * N / (ms_step * 1e-3) / 1e9,
+                "resolution": mech,
+                "register_kernel_ms_on_hierarchical_modes": {str(n): v for n, v in alt.items()},
                 "call_ms": call, "kernel_ms": kern,
                 "per_mode_gnnz_s": [nnz / (x * 1e-3) / 1e9 for x in call],
                 "bytes_per_nnz": per_nnz,
                 "kernel_gbs": [nnz * per_nnz / (x * 1e-3) / 1e9 for x in kern],
             }
             log(f"R={R} {tag}: all-mode step {ms_step:.3f} ms, kernel ms/mode "
-                f"{[round(x, 3) for x in kern]}")
+                f"{[round(x, 3) for x in kern]} ({mech}); register-based on the hierarchical "
+                f"modes: {({n: round(v, 3) for n, v in alt.items()})}")
             if head is None:
                 head = (R, ms_step, kern, per_nnz, A, F32, BF16, outs)
     R, ms_step, kern, per_nnz, A, F32, BF16, outs = head
@@ -197,7 +211,9 @@ def leg_inmemory(args, torch, blco, synth, w):
     res["roofline"] = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-        "kernel": win_kernel_name(R, N),
+        "kernel": [short_kernel_name(R, N) if T.resolution(n, R) == "hierarchical"
+                   else win_kernel_name(R, N) for n in modes]
+        if any(T.resolution(n, R) == "hierarchical" for n in modes) else win_kernel_name(R, N),
         "bytes_per_nnz": per_nnz, "avg_kernel_ms": avg_kernel_ms,
         "compulsory_bytes_per_launch": compulsory,
     }
@@ -404,6 +420,12 @@ def win_kernel_name(R, N, ft="float", big=False):
     return f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {'true' if big else 'false'}>"
 
 
+def short_kernel_name(R, N, ft="float", big=False):
+    """Template name of the hierarchical MTTKRP kernel for a single rank slice of width R."""
+    rpl = 1 if R <= 16 else 2 if R <= 32 else 4
+    return f"k_mttkrp_short<{rpl}, {ft}, {N}, {'true' if big else 'false'}>"
+
+
 def summarize_pmc(fetch_csv, write_csv, copy_bytes, kernel=None, out=TRAFFIC_FILE):
     """Per-launch HBM bytes of the MTTKRP kernel from two rocprofv3 --pmc runs.
 
@@ -462,6 +484,39 @@ def summarize_pmc(fetch_csv, write_csv, copy_bytes, kernel=None, out=TRAFFIC_FIL
     print("\n".join(lines))
 
 
+def resolution_sweep(args, torch, blco, synth):
+    """Both conflict-resolution mechanisms (Sections 5.1-5.2) on the short mode of
+    3-mode 2^21 x 2^17 x I tensors (Zipf(1.1) long modes, uniform short mode),
+    for the Section 5.3 heuristic: kernel ms of the mode-3 MTTKRP per mechanism."""
+    R = args.rank
+    nnz = args.nnz or 50_000_000
+    timer = Timer(torch)
+    rows = []
+    for I in (1, 2, 4, 8, 16, 32, 64, 128, 255, 512):
+        dims = (1 << 21, 1 << 17, I)
+        w = synth.Workload(f"short3_{I}", dims, nnz, (("zipf", 1.1), ("zipf", 1.1), ("uniform",)),
+                           "u01", (R,), (0, 1, 2), synth.BASE_SEED * 100 + 50 + I % 41)
+        coords, vals = synth.workload_tensor(w)
+        T = blco.build(coords, vals, dims)
+        A = synth.workload_factors(w, R)
+        F = [torch.from_numpy(a).to("cuda:0") for a in A]
+        out = torch.zeros((I, R), device="cuda:0")
+        ms = {}
+        for res in ("register", "hierarchical"):
+            T.set_resolution(res)
+            ms[res] = timer(lambda: blco.mttkrp_acc(T, 2, F, out), args.steps, args.warmup)
+        T.set_resolution("auto")
+        rows.append({"I": I, "nnz": len(vals), "register_ms": ms["register"],
+                     "hierarchical_ms": ms["hierarchical"], "auto": T.resolution(2, R),
+                     "register_over_hierarchical": ms["register"] / ms["hierarchical"]})
+        log(f"I={I}: register {ms['register']:.3f} ms, hierarchical {ms['hierarchical']:.3f} ms, "
+            f"auto picks {rows[-1]['auto']}")
+        T.free()
+        del F, A, coords, vals
+    return {"sweep": "conflict resolution vs short-mode length", "rank": R,
+            "cus": torch.cuda.get_device_properties(0).multi_processor_count, "rows": rows}
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
         summarize_pmc(sys.argv[2], sys.argv[3], int(sys.argv[4]))
@@ -471,11 +526,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zipf3",
-                    choices=["zipf3", "uniform3", "zipf4", "oom3", "cpgrad4", "small"])
+                    choices=["zipf3", "uniform3", "zipf4", "oom3", "cpgrad4", "short4", "small"])
     ap.add_argument("--nnz", type=int, default=None, help="shrink the workload (same recipe)")
     ap.add_argument("--budget", type=int, default=None, help="device budget for oom3 (bytes)")
     ap.add_argument("--cpu-sample-nnz", type=int, default=4_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--resolution-sweep", action="store_true",
+                    help="time both conflict-resolution mechanisms over short-mode lengths")
+    ap.add_argument("--rank", type=int, default=32, help="rank of --resolution-sweep")
     ap.add_argument("--calibrate-copy-bytes", type=int, default=0,
                     help="also run one plain device-to-device copy of this many bytes "
                          "(the reference for HBM traffic counters)")
@@ -499,6 +557,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.resolution_sweep:
+        print(json.dumps(resolution_sweep(args, torch, blco, synth)), flush=True)
+        return
     w = synth.WORKLOADS[args.workload]
     if args.workload == "oom3":
         res = leg_oom(args, torch, blco, synth, w)

@@ -55,6 +55,11 @@ extern "C" {
 #define BLCO_F32 0
 #define BLCO_BF16 1
 
+/* conflict resolution of the MTTKRP calls (Sections 5.1-5.3) */
+#define BLCO_RES_AUTO 0         /* Section 5.3: HIERARCHICAL when I_mode < compute units, else REGISTER */
+#define BLCO_RES_REGISTER 1     /* Section 5.2: segment sums in registers, one atomic per segment */
+#define BLCO_RES_HIERARCHICAL 2 /* Section 5.1: segment sums into a per-workgroup LDS stash */
+
 /* where blco_build places the non-zeros */
 #define BLCO_PLACE_DEVICE 0 /* device memory: in-memory MTTKRP */
 #define BLCO_PLACE_PINNED 1 /* pinned host memory: streamed by blco_mttkrp_stream */
@@ -181,6 +186,30 @@ int blco_mttkrp_stream_all(blco_tensor* t, const void* const* factors, int facto
  */
 int blco_sampled_loss(blco_tensor* t, const void* const* factors, int factor_dtype, int rank,
                       float* residual, double* loss, void* stream);
+
+/*
+ * Choose the conflict-resolution mechanism of every later MTTKRP call on t
+ * (blco_mttkrp*, blco_mttkrp_stream*, the CP gradient), Sections 5.1-5.3:
+ *   BLCO_RES_REGISTER: each window of non-zeros is sorted by target row and
+ *     every segment is summed in registers and added to the output with one
+ *     atomic per rank (Section 5.2);
+ *   BLCO_RES_HIERARCHICAL: each workgroup adds its segment sums into a private
+ *     copy of the output rows in LDS and adds that copy to the output once, at
+ *     its end (Section 5.1).  The copy holds I_mode rows of a slice of at least 16
+ *     ranks in 64 KiB of LDS next to the records of a 1024-non-zero batch: a
+ *     mode longer than 895 - 64 (N + 1) rows cannot use it, and its calls then
+ *     fail with EUNSUPPORTED;
+ *   BLCO_RES_AUTO (the default): the heuristic of Section 5.3, HIERARCHICAL
+ *     when the target mode is shorter than the device's compute units (256 on
+ *     MI355X), REGISTER otherwise.
+ * Results agree to rounding (the order of additions differs).  Errors: EINVAL.
+ */
+int blco_set_resolution(blco_tensor* t, int resolution);
+
+/* The mechanism (BLCO_RES_REGISTER or BLCO_RES_HIERARCHICAL) a mode-`mode`
+   MTTKRP call at rank `rank` on the current device uses, in *chosen.
+   Errors: EINVAL, EUNSUPPORTED (HIERARCHICAL forced on a mode too long). */
+int blco_resolution(const blco_tensor* t, int mode, int rank, int* chosen);
 
 /* dst[i] = bf16(src[i]), round to nearest even (NaN stays NaN); device arrays. */
 int blco_cast_bf16(const float* src, uint16_t* dst, int64_t n, void* stream);

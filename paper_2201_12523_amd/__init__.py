@@ -32,7 +32,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: 
 
 EXPORTED = ["blco_build", "blco_mttkrp", "blco_mttkrp_acc", "blco_mttkrp_v", "blco_mttkrp_stream",
             "blco_mttkrp_stream_all",
-            "blco_sampled_loss", "blco_cast_bf16", "blco_info", "blco_export", "blco_free",
+            "blco_sampled_loss", "blco_cast_bf16", "blco_set_resolution", "blco_resolution",
+            "blco_info", "blco_export", "blco_free",
             "blco_last_error"]
 
 
@@ -83,6 +84,8 @@ def lib():
         L.blco_cast_bf16.argtypes = [p, p, i64, p]
         L.blco_info.argtypes = [p, ctypes.POINTER(_Info)]
         L.blco_export.argtypes = [p, p, p, p, p]
+        L.blco_set_resolution.argtypes = [p, i32]
+        L.blco_resolution.argtypes = [p, i32, i32, ctypes.POINTER(ctypes.c_int)]
         L.blco_free.argtypes = [p]
         L.blco_free.restype = None
         L.blco_last_error.restype = ctypes.c_char_p
@@ -102,6 +105,9 @@ def _stream(stream=None) -> int:
     if stream is None:
         stream = torch.cuda.current_stream()
     return int(stream.cuda_stream)
+
+
+RESOLUTIONS = {"auto": 0, "register": 1, "hierarchical": 2}
 
 
 class BLCOTensor:
@@ -135,6 +141,19 @@ class BLCOTensor:
     @property
     def nmodes(self) -> int:
         return len(self.dims)
+
+    def set_resolution(self, resolution: str):
+        """Conflict resolution of later MTTKRP calls: "auto" (Section 5.3 heuristic),
+        "register" (Section 5.2) or "hierarchical" (Section 5.1)."""
+        if resolution not in RESOLUTIONS:
+            raise ValueError(f"resolution {resolution!r}: one of {sorted(RESOLUTIONS)}")
+        _check(lib().blco_set_resolution(self._h, RESOLUTIONS[resolution]))
+
+    def resolution(self, mode: int, rank: int) -> str:
+        """The mechanism a mode-`mode` MTTKRP at rank `rank` uses on the current device."""
+        c = ctypes.c_int(-1)
+        _check(lib().blco_resolution(self._h, int(mode), int(rank), ctypes.byref(c)))
+        return {v: k for k, v in RESOLUTIONS.items()}[c.value]
 
     def export(self):
         """(keys uint64, values float32, block_ids uint64, block_starts int64) on the host."""

@@ -600,8 +600,221 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
 }
 
 // ---------------------------------------------------------------------------
-// BLCO MTTKRP with hierarchical conflict resolution through an LDS stash
-// (Section 5.1, steps 5-6), the default kernel.
+// BLCO MTTKRP with hierarchical conflict resolution (Section 5.1, steps 1-6),
+// the mechanism the heuristic of Section 5.3 picks for short target modes.
+//
+// Each workgroup owns a contiguous range of the ALTO-ordered non-zeros and a
+// slice of at most 64 ranks (blockIdx.y), and keeps a private copy of that
+// slice of all I_n output rows in LDS (the stash; it covers every target row,
+// so no lookup is needed).  Per batch of kShortB non-zeros:
+//   processing: one non-zero per thread is loaded (coalesced) and decoded by
+//     shift and mask; the batch is grouped by target row with a counting sort
+//     (LDS histogram with atomic ranks, exclusive scan, scatter), and each
+//     grouped position gets a record: byte offsets of the other modes' factor
+//     rows, target row, value;
+//   computing: each group of LPN lanes (RPL ranks per lane) walks LPN
+//     consecutive grouped positions, kShortLoads / RPL at a time, gathering
+//     the other modes' rows and summing the scaled Hadamard products in
+//     registers while the target stays the same;
+//   stash update: a target's positions form one run, so each run has one
+//     owner, the group holding its first position.  A group whose first
+//     segment continues a run from an earlier group leaves that partial sum
+//     in a per-group carry slot; after a barrier the owner of a run that
+//     crosses into later groups adds their carries.  Every owner then adds its
+//     run's sum into the stash row with a plain LDS read-modify-write: no two
+//     lanes touch one stash entry in a batch, so no LDS atomics are needed
+//     (fp32 LDS atomics measured several times slower than this on gfx950).
+// When the range is done the stash is added to the output with one global
+// atomic per (row, rank) that received any term, so an output row sees one
+// update per workgroup instead of one per window.
+constexpr int kShortB = 1024;               // threads = non-zeros per batch
+constexpr int kShortLPN = 16;               // lanes per position
+constexpr int kShortNG = kShortB / kShortLPN;   // lane groups = positions per group
+constexpr int kShortHist = 1024;            // histogram bins (>= I_n)
+constexpr int kShortLds = 64 * 1024;        // records + histogram + carries + stash
+constexpr int kShortLoads = 8;              // positions x ranks in flight per lane
+
+// LDS bytes besides the stash: records, histogram, scan totals, carry slots
+// (one per group, cls = 16, 32 or 64 floats: the ranks one group covers)
+__host__ __device__ constexpr size_t short_fixed_lds(int N, int cls) {
+  return (size_t)kShortB * (N + 1) * 4 + (size_t)kShortHist * 4 + (kShortB / 64) * 4 +
+         (size_t)kShortNG * cls * 4;
+}
+
+template <int RPL, typename FT, int N, bool BIG>
+__global__ __launch_bounds__(kShortB, 8) void k_mttkrp_short(KParams p, int64_t per) {
+  extern __shared__ __align__(16) unsigned char smem_short[];
+  constexpr int LPN = kShortLPN;
+  constexpr int NF = N + 1;
+  constexpr int NG = kShortNG;
+  constexpr int C = kShortB / NG;            // positions per group and batch
+  constexpr int U = kShortLoads / RPL;       // positions in flight per group
+  constexpr int CW = LPN * RPL;              // ranks one group covers (carry slot)
+  const int I = (int)p.short_rows;
+  const int SW = p.short_width;              // <= CW
+  const int rlo = (int)blockIdx.y * SW;
+  const int W = min(SW, p.R - rlo);
+  uint32_t* s_rec = reinterpret_cast<uint32_t*>(smem_short);    // kShortB x NF
+  uint32_t* s_hist = s_rec + kShortB * NF;                      // kShortHist
+  uint32_t* s_wsum = s_hist + kShortHist;                       // kShortB / 64
+  float* s_carry = reinterpret_cast<float*>(s_wsum + kShortB / 64);   // NG x CW
+  float* s_out = s_carry + NG * CW;                             // I x SW
+  const int tid = threadIdx.x;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = min(p.n, lo + per);
+  if (lo >= hi || W <= 0) return;
+  for (int i = tid; i < I * SW; i += kShortB) s_out[i] = 0.f;
+  for (int i = tid; i < kShortHist; i += kShortB) s_hist[i] = 0;
+  const int gi = tid / LPN, rl = tid % LPN;
+  constexpr int NO = N > 1 ? N - 1 : 1;
+  __amdgpu_buffer_rsrc_t rs[NO];
+  const void* ap[NO];
+#pragma unroll
+  for (int j = 0; j + 1 < N; ++j) {
+    const int m = (j < p.mode) ? j : j + 1;
+    ap[j] = p.A[m];
+    rs[j] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.A[m]), 0, (int)p.abytes[m],
+                                              (int)kBufFlags);
+  }
+  uint32_t loff[RPL];
+  bool ract[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int r = rl + q * LPN;
+    ract[q] = r < W;
+    loff[q] = (uint32_t)(rlo + (ract[q] ? r : 0)) * (uint32_t)sizeof(FT);
+  }
+  for (int64_t b0 = lo; b0 < hi; b0 += kShortB) {
+    // ---- processing: load, decode, group by target
+    __syncthreads();   // histogram cleared; the previous batch's records and carries consumed
+    const int64_t k = b0 + tid;
+    const bool valid = k < hi;
+    uint32_t c[N];
+    float x = 0.f;
+    uint32_t tgt = 0, rank = 0;
+    if (valid) {
+      decode<N>(p, p.keys[k], p.base + k, c);
+      x = p.vals[k];
+#pragma unroll
+      for (int m = 0; m < N; ++m)
+        if (m == p.mode) tgt = c[m];
+      rank = atomicAdd(&s_hist[tgt], 1u);
+    }
+    __syncthreads();
+    block_exclusive_scan<kShortHist, kShortB>(s_hist, tid, s_wsum);
+    if (valid) {
+      const int pos = (int)(s_hist[tgt] + rank);
+#pragma unroll
+      for (int j = 0; j + 1 < N; ++j)
+        s_rec[pos * NF + j] = ((j < p.mode) ? c[j] : c[j + 1]) * (BIG ? 1u : p.rowbytes);
+      s_rec[pos * NF + N - 1] = tgt;
+      s_rec[pos * NF + N] = __float_as_uint(x);
+    }
+    __syncthreads();
+    // ---- computing: segment sums of this group's positions
+    const int nb = (int)min<int64_t>(kShortB, hi - b0);
+    const int q0 = gi * C;
+    const int qe = min(q0 + C, nb);
+    float acc[RPL];
+    uint32_t cur = 0;
+    bool pending = false;   // owner of a run that continues into later groups
+    int run_end = 0;        // end of that run (grouped position)
+    if (q0 < qe) {
+      cur = s_rec[q0 * NF + N - 1];
+      const bool first_shared = q0 > 0 && s_rec[(q0 - 1) * NF + N - 1] == cur;
+      const bool last_cont = qe < nb && s_rec[qe * NF + N - 1] == s_rec[(qe - 1) * NF + N - 1];
+      bool first = true;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) acc[q] = 0.f;
+      for (int j0 = q0; j0 < qe; j0 += U) {
+        float pr[U][RPL];
+        uint32_t tg[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int j = j0 + u;
+          const uint32_t* e = &s_rec[(j < qe ? j : j0) * NF];
+          const float xv = __uint_as_float(e[N]);
+          tg[u] = e[N - 1];
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) pr[u][q] = xv;
+#pragma unroll
+          for (int jj = 0; jj + 1 < N; ++jj) {
+            if constexpr (BIG) {
+              const FT* rowp = static_cast<const FT*>(ap[jj]) + (size_t)e[jj] * p.R;
+#pragma unroll
+              for (int q = 0; q < RPL; ++q)
+                pr[u][q] *= ld_factor<FT>(rowp, (size_t)(loff[q] / sizeof(FT)));
+            } else {
+#pragma unroll
+              for (int q = 0; q < RPL; ++q) pr[u][q] *= ld_buf<FT>(rs[jj], e[jj] + loff[q]);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (j0 + u >= qe) break;
+          if (tg[u] != cur) {
+            // a finished segment that does not reach the end of this group
+            if (first && first_shared) {
+#pragma unroll
+              for (int q = 0; q < RPL; ++q) s_carry[gi * CW + rl + q * LPN] = acc[q];
+            } else {
+#pragma unroll
+              for (int q = 0; q < RPL; ++q)
+                if (ract[q]) s_out[cur * SW + rl + q * LPN] += acc[q];
+            }
+            first = false;
+            cur = tg[u];
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) acc[q] = 0.f;
+          }
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) acc[q] += pr[u][q];
+        }
+      }
+      // the segment that reaches the end of this group
+      if (first && first_shared) {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) s_carry[gi * CW + rl + q * LPN] = acc[q];
+      } else if (last_cont) {
+        pending = true;
+        // the scanned histogram holds each target's first position, so the
+        // run of `cur` ends where the next target's begins
+        run_end = cur + 1 < (uint32_t)kShortHist ? (int)s_hist[cur + 1] : nb;
+      } else {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q)
+          if (ract[q]) s_out[cur * SW + rl + q * LPN] += acc[q];
+      }
+    }
+    __syncthreads();
+    // ---- owners of runs that cross groups add the later groups' carries
+    if (pending) {
+#pragma unroll 4
+      for (int g2 = gi + 1; g2 * C < run_end; ++g2) {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) acc[q] += s_carry[g2 * CW + rl + q * LPN];
+      }
+#pragma unroll
+      for (int q = 0; q < RPL; ++q)
+        if (ract[q]) s_out[cur * SW + rl + q * LPN] += acc[q];
+    }
+    for (int i = tid; i < kShortHist; i += kShortB) s_hist[i] = 0;
+  }
+  __syncthreads();
+  // ---- one global atomic per stash entry that received a term
+  const float scale = term_scale(p);
+  for (int i = tid; i < I * W; i += kShortB) {
+    const int row = i / W, r = i - row * W;
+    const float v = s_out[row * SW + r];
+    if (v != 0.f) unsafeAtomicAdd(p.out + (size_t)row * p.R + rlo + r, v * scale);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BLCO MTTKRP with hierarchical conflict resolution through a hashed LDS stash
+// (Section 5.1, steps 5-6) for target modes of any length; a variant kept for
+// comparison (BLCO_KERNEL=stash).
 //
 // Persistent workgroups of kSB threads each own a contiguous range of the
 // ALTO-ordered non-zeros and walk it in batches of kSB:
@@ -970,6 +1183,69 @@ static KernelFn pick_win(int N) {
 }
 
 typedef void (*StashFn)(KParams, StashCfg);
+typedef void (*ShortFn)(KParams, int64_t);
+
+template <int RPL, typename FT, bool BIG>
+static ShortFn pick_short(int N) {
+  switch (N) {
+    case 1: return k_mttkrp_short<RPL, FT, 1, BIG>;
+    case 2: return k_mttkrp_short<RPL, FT, 2, BIG>;
+    case 3: return k_mttkrp_short<RPL, FT, 3, BIG>;
+    case 4: return k_mttkrp_short<RPL, FT, 4, BIG>;
+    case 5: return k_mttkrp_short<RPL, FT, 5, BIG>;
+    case 6: return k_mttkrp_short<RPL, FT, 6, BIG>;
+    case 7: return k_mttkrp_short<RPL, FT, 7, BIG>;
+    default: return k_mttkrp_short<RPL, FT, 8, BIG>;
+  }
+}
+
+// ranks per lane of the hierarchical kernel for a slice width (<= 64)
+static int short_rpl(int SW) { return SW <= 16 ? 1 : SW <= 32 ? 2 : 4; }
+
+template <typename FT, bool BIG>
+static ShortFn select_short_t(int N, int SW) {
+  const int rpl = short_rpl(SW);
+  if (rpl == 1) return pick_short<1, FT, BIG>(N);
+  if (rpl == 2) return pick_short<2, FT, BIG>(N);
+  return pick_short<4, FT, BIG>(N);
+}
+
+static ShortFn select_short(int N, int SW, int fdt, bool big) {
+  if (fdt == BLCO_F32)
+    return big ? select_short_t<float, true>(N, SW) : select_short_t<float, false>(N, SW);
+  return big ? select_short_t<uint16_t, true>(N, SW) : select_short_t<uint16_t, false>(N, SW);
+}
+
+static size_t short_lds(int N, uint64_t rows, int SW) {
+  return short_fixed_lds(N, kShortLPN * short_rpl(SW)) + (size_t)rows * SW * sizeof(float);
+}
+
+// Rank-slice width of the hierarchical kernel: slices of at most 64 ranks, as
+// even as possible, in multiples of 16 when there are several, such that the
+// stash (I_n x SW fp32), the records, the histogram and the carry slots fit in
+// kShortLds bytes.  0 when even a 16-rank slice does not fit.
+static int short_slice_width(int N, uint64_t rows, int R) {
+  if (rows > (uint64_t)kShortHist) return 0;
+  for (int slices = (R + 63) / 64; slices <= (R + 15) / 16; ++slices) {
+    const int w = slices == 1 ? R : ((R + slices - 1) / slices + 15) / 16 * 16;
+    if (short_lds(N, rows, w) <= (size_t)kShortLds) return w;
+  }
+  return 0;
+}
+
+// Compute units of the current device (the Section 5.3 threshold), read once per device.
+static int device_cus() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+      v = 256;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
 
 template <int V, typename FT>
 static StashFn pick_stash(int N) {
@@ -1095,6 +1371,25 @@ static int kernel_variant() {
   return g_variant;
 }
 
+// Conflict-resolution mechanism of a mode-`mode` MTTKRP at rank R (Section
+// 5.3): the tensor's setting, where AUTO takes the hierarchical mechanism when
+// the target mode is shorter than the device's compute units.  *sw receives
+// the hierarchical kernel's rank-slice width.
+static int resolve(const blco_tensor* t, int mode, int rank, int* sw) {
+  const uint64_t rows = t->lay.dims[mode];
+  const int w = short_slice_width(t->lay.N, rows, rank);
+  *sw = w;
+  if (t->resolution == BLCO_RES_REGISTER) return BLCO_RES_REGISTER;
+  if (t->resolution == BLCO_RES_HIERARCHICAL) {
+    if (!w)
+      return set_error(BLCO_EUNSUPPORTED,
+                       "hierarchical resolution: mode %d (%llu rows) does not fit the LDS stash",
+                       mode, (unsigned long long)rows);
+    return BLCO_RES_HIERARCHICAL;
+  }
+  return (w && rows < (uint64_t)device_cus()) ? BLCO_RES_HIERARCHICAL : BLCO_RES_REGISTER;
+}
+
 // ====================================================================== host runtime
 
 static size_t factor_elem_bytes(int fdt) { return fdt == BLCO_BF16 ? 2 : 4; }
@@ -1137,7 +1432,9 @@ static int check_factor_args(const blco_tensor* t, int mode, const void* const* 
     if ((m != mode || need_mode_factor) && !factors[m] && t->nnz > 0)
       return set_error(BLCO_EINVAL, "factors[%d] is NULL", m);
   if (!out) return set_error(BLCO_EINVAL, "out is NULL");
-  return BLCO_OK;
+  int sw = 0;
+  const int res = resolve(t, mode, rank, &sw);
+  return res < 0 ? res : BLCO_OK;
 }
 
 // Launch the MTTKRP kernel over [lo, lo + n) of the tensor given by keys/vals.
@@ -1170,6 +1467,24 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
     const size_t bytes = (size_t)t->lay.dims[m] * rank * fsz;
     p.abytes[m] = (uint32_t)std::min<size_t>(bytes, 0xFFFFFFFFull);
     if (m != mode && bytes > 0xFFFFFFFFull) big = true;
+  }
+  int sw = 0;
+  const int res = resolve(t, mode, rank, &sw);
+  if (res < 0) return res;
+  if (res == BLCO_RES_HIERARCHICAL) {
+    p.short_rows = (uint32_t)t->lay.dims[mode];
+    p.short_width = sw;
+    const int slices = (rank + sw - 1) / sw;
+    // two resident workgroups per CU over all slices; each takes an equal range
+    const int64_t want = std::max<int64_t>(device_cus() * 2 / slices, 1);
+    int64_t per = std::max<int64_t>((n + want - 1) / want, (int64_t)kShortB * 4);
+    per = (per + kShortB - 1) / kShortB * kShortB;
+    const int64_t nwg = (n + per - 1) / per;
+    const size_t lds = short_lds(t->lay.N, t->lay.dims[mode], sw);
+    ShortFn f = select_short(t->lay.N, sw, fdt, big);
+    hipLaunchKernelGGL(f, dim3((unsigned)nwg, (unsigned)slices), dim3(kShortB), lds, s, p, per);
+    HIPCHK(hipGetLastError());
+    return BLCO_OK;
   }
   if (var == kVarNaive) {
     int64_t threads = n * (int64_t)rank;
@@ -1582,6 +1897,30 @@ extern "C" int blco_sampled_loss(blco_tensor* t, const void* const* factors, int
   hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(1024), 0, s, (const double*)t->d_partials,
                      blocks, loss);
   HIPCHK(hipGetLastError());
+  return BLCO_OK;
+}
+
+extern "C" int blco_set_resolution(blco_tensor* t, int resolution) {
+  clear_error();
+  if (!t) return set_error(BLCO_EINVAL, "tensor is NULL");
+  if (resolution != BLCO_RES_AUTO && resolution != BLCO_RES_REGISTER &&
+      resolution != BLCO_RES_HIERARCHICAL)
+    return set_error(BLCO_EINVAL, "resolution %d", resolution);
+  t->resolution = resolution;
+  return BLCO_OK;
+}
+
+extern "C" int blco_resolution(const blco_tensor* t, int mode, int rank, int* chosen) {
+  clear_error();
+  if (!t) return set_error(BLCO_EINVAL, "tensor is NULL");
+  if (mode < 0 || mode >= t->lay.N)
+    return set_error(BLCO_EINVAL, "mode %d outside 0..%d", mode, t->lay.N - 1);
+  if (rank < 1) return set_error(BLCO_EINVAL, "rank %d < 1", rank);
+  if (!chosen) return set_error(BLCO_EINVAL, "chosen is NULL");
+  int sw = 0;
+  const int res = resolve(t, mode, rank, &sw);
+  if (res < 0) return res;
+  *chosen = res;
   return BLCO_OK;
 }
 

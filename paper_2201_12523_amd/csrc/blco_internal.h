@@ -68,6 +68,7 @@ struct blco_tensor {
   size_t stream_peak_bytes = 0;
   int64_t stream_chunks = 0;
   int device = -1;
+  int resolution = BLCO_RES_AUTO;   // conflict resolution (blco_set_resolution)
 };
 
 namespace blco {

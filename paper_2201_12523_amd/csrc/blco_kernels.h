@@ -30,6 +30,8 @@ struct KParams {
   uint32_t mask[8];
   int wide;                   // target index too long for 32-bit sort keys
   int xcd_remap;              // give consecutive windows to the same XCD
+  uint32_t short_rows;        // hierarchical kernel: target mode length
+  int short_width;            // hierarchical kernel: ranks per slice
   uint32_t rowbytes;          // bytes of one factor row (R x element size)
   uint32_t abytes[8];         // bytes of each factor matrix (clamped to 2^32 - 1)
   float scale;                // host-side scale of every term

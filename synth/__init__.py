@@ -118,6 +118,10 @@ WORKLOADS = {
     # CP-gradient: 2^20 x 2^18 x 2^16 x 2^12, 80M Zipf(1.1), rank-8 model + noise, R=32
     "cpgrad4": Workload("cpgrad4", (1 << 20, 1 << 18, 1 << 16, 1 << 12), 80_000_000,
                         (_z(1.1),) * 4, "cp8", (32,), (0, 1, 2, 3), BASE_SEED * 100 + 4),
+    # short modes: 2^21 x 2^17 x 24 x 168, 50M, Zipf(1.1) on the long modes and uniform on
+    # the two modes shorter than the compute-unit count (hierarchical resolution), R=32
+    "short4": Workload("short4", (1 << 21, 1 << 17, 24, 168), 50_000_000,
+                       (_z(1.1), _z(1.1), U, U), "u01", (32,), (0, 1, 2, 3), BASE_SEED * 100 + 6),
 }
 
 

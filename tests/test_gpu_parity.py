@@ -53,8 +53,21 @@ def check_entries(got, M, S, tol=TOL, label=""):
     return worst
 
 
+def hierarchical_fits(t, n, R):
+    """Whether mode n at rank R can take hierarchical conflict resolution."""
+    t.set_resolution("hierarchical")
+    try:
+        t.resolution(n, R)
+        return True
+    except blco.BLCOError as e:
+        assert e.status == "EUNSUPPORTED"
+        return False
+
+
 def run_case(coords, vals, dims, R, modes=None, key_bits=64, cap=1 << 27, seed=0,
-             dtypes=("fp32",), label=""):
+             dtypes=("fp32",), label="", resolutions=("register", "hierarchical")):
+    """Every mode under each conflict-resolution mechanism (hierarchical only where
+    the mode fits its LDS stash) against the oracle."""
     say(f"case {label} dims={dims} nnz={len(vals)} R={R} key_bits={key_bits} cap={cap}")
     t = blco.build(coords, vals, dims, key_bits=key_bits, max_block_nnz=cap)
     rng = np.random.default_rng(seed)
@@ -68,14 +81,21 @@ def run_case(coords, vals, dims, R, modes=None, key_bits=64, cap=1 << 27, seed=0
             F = _dev_factors(A, torch.bfloat16)
             Aref = [_bf16_round(a) for a in A]
         for n in modes:
-            out = blco.mttkrp(t, n, F)
-            torch.cuda.synchronize()
             M, S = oracle.mttkrp(coords, vals, Aref, n)
-            check_entries(out.cpu().numpy(), M, S, label=f"{label} {dt} mode {n}")
-            if dt == "bf16":
-                M32, S32 = oracle.mttkrp(coords, vals, A, n)
-                bound = (len(dims) - 1) * 2.0 ** -8 + 1e-5
-                check_entries(out.cpu().numpy(), M32, S32, tol=bound, label=f"{label} bf16-vs-fp32")
+            for res in resolutions:
+                if res == "hierarchical" and not hierarchical_fits(t, n, R):
+                    continue
+                t.set_resolution(res)
+                assert t.resolution(n, R) == res
+                out = blco.mttkrp(t, n, F)
+                torch.cuda.synchronize()
+                tag = f"{label} {dt} {res} mode {n}"
+                check_entries(out.cpu().numpy(), M, S, label=tag)
+                if dt == "bf16":
+                    M32, S32 = oracle.mttkrp(coords, vals, A, n)
+                    bound = (len(dims) - 1) * 2.0 ** -8 + 1e-5
+                    check_entries(out.cpu().numpy(), M32, S32, tol=bound,
+                                  label=f"{tag} bf16-vs-fp32")
     t.free()
 
 
@@ -183,13 +203,15 @@ def test_bf16_factors():
     run_case(coords, vals, w.dims, 32, seed=5, dtypes=("bf16",), label="bf16")
 
 
-def test_mttkrp_v_scaled():
+@pytest.mark.parametrize("res", ["register", "hierarchical"])
+def test_mttkrp_v_scaled(res):
     rng = np.random.default_rng(21)
     dims = (50, 40, 30)
     nnz = 2000
     coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
     vals = rng.random(nnz).astype(np.float32)
     t = blco.build(coords, vals, dims)
+    t.set_resolution(res)
     _, v_blco, _, _ = t.export()
     A = [rng.standard_normal((d, 16)).astype(np.float32) for d in dims]
     F = _dev_factors(A)
@@ -228,14 +250,16 @@ def test_sampled_loss_and_residual():
     assert torch.equal(resid, resid2)
 
 
+@pytest.mark.parametrize("res", ["register", "hierarchical"])
 @pytest.mark.parametrize("storage", ["fp32", "bf16"])
-def test_cp_gradient(storage):
+def test_cp_gradient(storage, res):
     rng = np.random.default_rng(41)
     dims = (40, 30, 20, 10)
     nnz = 3000
     coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
     vals = rng.standard_normal(nnz).astype(np.float32)
     t = blco.build(coords, vals, dims)
+    t.set_resolution(res)
     A = [(rng.standard_normal((d, 32)) * 0.6).astype(np.float32) for d in dims]
     P = [torch.from_numpy(a).to(DEV).requires_grad_(True) for a in A]
     loss = blco.CPLoss.apply(t, storage, *P)
@@ -283,8 +307,9 @@ def test_cast_bf16_matches_torch():
     assert blco.cast_bf16(z).float().cpu().tolist() == [1.0, 1.0 + 2 ** -6]
 
 
+@pytest.mark.parametrize("res", ["register", "hierarchical"])
 @pytest.mark.parametrize("budget_nnz", [64, 1000, 5000])
-def test_stream_matches_in_memory(budget_nnz):
+def test_stream_matches_in_memory(budget_nnz, res):
     rng = np.random.default_rng(budget_nnz)
     dims = (300, 200, 100)
     nnz = 20_000
@@ -294,6 +319,7 @@ def test_stream_matches_in_memory(budget_nnz):
     A = [rng.standard_normal((d, R)).astype(np.float32) for d in dims]
     F = _dev_factors(A)
     tp = blco.build(coords, vals, dims, placement="pinned")
+    tp.set_resolution(res)
     for n in range(3):
         fixed = dims[n] * R * 4 + sum(dims[m] * R * 4 for m in range(3) if m != n)
         fixed += tp.info()["device_bytes"]

@@ -134,3 +134,31 @@ def test_exports_every_declared_symbol():
     L = ctypes.CDLL(blco.library_path())
     for d in declared:
         assert getattr(L, d) is not None
+
+
+def test_resolution_setting_and_heuristic():
+    """Section 5.3: the hierarchical mechanism for a target mode shorter than the
+    compute-unit count (at least 100 on any device this runs on), the register-based
+    one otherwise; a forced choice sticks, and a mode too long for the LDS stash
+    rejects the hierarchical one."""
+    _lib_or_skip()
+    rng = np.random.default_rng(2)
+    dims = (100, 5000, 7)
+    coords = [rng.integers(0, d, size=500).astype(np.uint32) for d in dims]
+    t = blco.build(coords, rng.random(500).astype(np.float32), dims, placement="host")
+    assert [t.resolution(n, 32) for n in range(3)] == ["hierarchical", "register", "hierarchical"]
+    t.set_resolution("register")
+    assert [t.resolution(n, 32) for n in range(3)] == ["register"] * 3
+    t.set_resolution("hierarchical")
+    assert t.resolution(0, 1000) == "hierarchical"   # split into rank slices
+    with pytest.raises(blco.BLCOError) as e:
+        t.resolution(1, 16)
+    assert e.value.status == "EUNSUPPORTED"
+    L = blco.lib()
+    assert L.blco_set_resolution(t.handle, 3) == -1
+    assert L.blco_set_resolution(None, 0) == -1
+    c = ctypes.c_int(-1)
+    assert L.blco_resolution(t.handle, 3, 32, ctypes.byref(c)) == -1
+    assert L.blco_resolution(t.handle, 0, 0, ctypes.byref(c)) == -1
+    t.set_resolution("auto")
+    assert L.blco_resolution(t.handle, 2, 8, ctypes.byref(c)) == 0 and c.value == 2
