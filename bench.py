@@ -215,6 +215,8 @@ def leg_inmemory(args, torch, blco, synth, w):
                    else win_kernel_name(R, N) for n in modes]
         if any(T.resolution(n, R) == "hierarchical" for n in modes) else win_kernel_name(R, N),
         "bytes_per_nnz": per_nnz, "avg_kernel_ms": avg_kernel_ms,
+        "model": "requested bytes 12 + (N-1)*R*s_f per non-zero (the paper's Vol); "
+                 "frac above 1 means factor rows are served from cache",
         "compulsory_bytes_per_launch": compulsory,
     }
     res["per_config"] = results
