@@ -214,6 +214,53 @@ int blco_resolution(const blco_tensor* t, int mode, int rank, int* chosen);
 /* dst[i] = bf16(src[i]), round to nearest even (NaN stays NaN); device arrays. */
 int blco_cast_bf16(const float* src, uint16_t* dst, int64_t n, void* stream);
 
+/*
+ * Gram matrix G = A^T A of a factor matrix (the factors of V in Algorithm 1):
+ * A device, rows x rank, fp32 or bf16 (dtype); G device, rank x rank fp64,
+ * overwritten.  Products are fp32 over 64 rows at a time, sums fp64; the
+ * workgroups add their sums with fp64 atomics, so G is not bitwise
+ * reproducible.  1 <= rank <= 64.  Errors: EINVAL.
+ */
+int blco_gram(const void* A, int dtype, int64_t rows, int rank, double* G, void* stream);
+
+typedef struct {
+  int max_iters;    /* iteration cap, >= 1 (NULL options: 25) */
+  double tol;       /* stop once an iteration raises the fit by less than tol (1e-5); a
+                       negative tol only stops on a fit drop larger than |tol| */
+  int factor_dtype; /* what the MTTKRP reads: BLCO_F32, or BLCO_BF16 copies refreshed from the
+                       fp32 factors after every update (BLCO_F32) */
+} blco_cpals_opts;
+
+typedef struct {
+  int iters;           /* iterations run */
+  int pinv_fallbacks;  /* updates whose V was singular to working precision */
+} blco_cpals_report;
+
+/*
+ * CP-ALS (Algorithm 1) on an in-memory tensor (placement DEVICE).  For each
+ * iteration and each mode n in turn:
+ *   V = Hadamard product of A^(m)T A^(m) over m != n (fp64),
+ *   M = mode-n MTTKRP (blco_mttkrp, the tensor's conflict resolution),
+ *   A^(n) = M V^+ (fp64 sums, stored fp32),
+ * then the fit 1 - ||X - [[A^(1..N)]]||_F / ||X||_F from the norm identity
+ * ||X||^2 - 2 <X, Xhat> + ||Xhat||^2 (<X, Xhat> from the last mode's M).
+ * Iterations stop after max_iters or once the fit rises by less than tol.
+ * V^+ is V^-1 by Gauss-Jordan elimination when every pivot exceeds
+ * 1e-13 * max diag(V); otherwise a rank-revealing pivoted Cholesky
+ * P^T V P = L L^T gives V^+ = P L (L^T L)^-2 L^T P^T (counted in the report).
+ * factors: host array of N device pointers to fp32 I_m x R matrices, the
+ * initial values, overwritten with the result.  fits: host array of
+ * max_iters doubles (may be NULL) receiving the fit after each iteration;
+ * report may be NULL.  1 <= rank <= 64.  Device workspace (largest I_m x R
+ * fp32, N + 4 R x R fp64, bf16 copies if asked) is allocated and freed by the
+ * call.  Synchronous: waits on `stream` once per iteration for the fit.
+ * The fit identity loses digits to cancellation once the residual is small:
+ * with fp32 MTTKRP outputs it is good to about 1e-4 near a fit of 1.
+ * Errors: EINVAL (placement, rank, options, empty tensor), ENOMEM, EDEVICE.
+ */
+int blco_cp_als(blco_tensor* t, float* const* factors, int rank, const blco_cpals_opts* opts,
+                double* fits, blco_cpals_report* report, void* stream);
+
 /* Layout, sizes and last streaming call statistics of a tensor (waits for the
    last streaming call to finish when it has not been measured yet). */
 int blco_info(const blco_tensor* t, blco_info_t* info);

@@ -35,12 +35,12 @@ def gram(A):
 
 
 def hadamard_of_grams(grams, skip=None):
-    """Entry-wise product of the given Gram matrices, leaving out index ``skip``."""
-    V = None
+    """Entry-wise product of the given Gram matrices, leaving out index ``skip``
+    (all ones, the identity of the entry-wise product, when nothing is left)."""
+    V = np.ones_like(grams[0])
     for m, G in enumerate(grams):
-        if m == skip:
-            continue
-        V = G.copy() if V is None else V * G
+        if m != skip:
+            V = V * G
     return V
 
 

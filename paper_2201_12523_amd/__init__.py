@@ -33,6 +33,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: 
 EXPORTED = ["blco_build", "blco_mttkrp", "blco_mttkrp_acc", "blco_mttkrp_v", "blco_mttkrp_stream",
             "blco_mttkrp_stream_all",
             "blco_sampled_loss", "blco_cast_bf16", "blco_set_resolution", "blco_resolution",
+            "blco_gram", "blco_cp_als",
             "blco_info", "blco_export", "blco_free",
             "blco_last_error"]
 
@@ -47,6 +48,14 @@ class BLCOError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("key_bits", ctypes.c_int), ("max_block_nnz", ctypes.c_int64),
                 ("placement", ctypes.c_int)]
+
+
+class _CPALSOpts(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int), ("tol", ctypes.c_double), ("factor_dtype", ctypes.c_int)]
+
+
+class _CPALSReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("pinv_fallbacks", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -85,6 +94,9 @@ def lib():
         L.blco_info.argtypes = [p, ctypes.POINTER(_Info)]
         L.blco_export.argtypes = [p, p, p, p, p]
         L.blco_set_resolution.argtypes = [p, i32]
+        L.blco_gram.argtypes = [p, i32, i64, i32, p, p]
+        L.blco_cp_als.argtypes = [p, p, i32, ctypes.POINTER(_CPALSOpts), p,
+                                  ctypes.POINTER(_CPALSReport), p]
         L.blco_resolution.argtypes = [p, i32, i32, ctypes.POINTER(ctypes.c_int)]
         L.blco_free.argtypes = [p]
         L.blco_free.restype = None
@@ -318,6 +330,38 @@ def cast_bf16(x, stream=None):
     y = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
     _check(lib().blco_cast_bf16(x.data_ptr(), y.data_ptr(), x.numel(), _stream(stream)))
     return y
+
+
+def gram(A, stream=None):
+    """A^T A as a float64 R x R device tensor (fp32 products, fp64 sums; library kernel)."""
+    if A.dim() != 2 or not A.is_contiguous() or A.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("A must be a contiguous 2-D float32 or bfloat16 tensor")
+    R = A.shape[1]
+    G = torch.empty((R, R), dtype=torch.float64, device=A.device)
+    dt = BF16 if A.dtype == torch.bfloat16 else F32
+    _check(lib().blco_gram(A.data_ptr(), dt, A.shape[0], R, G.data_ptr(), _stream(stream)))
+    return G
+
+
+def cp_als(t, factors, max_iters=25, tol=1e-5, storage="fp32", stream=None):
+    """CP-ALS (Algorithm 1) on the device; `factors` (fp32 I_m x R device tensors) are the
+    initial values and are overwritten.  Returns (fits per iteration, report dict)."""
+    for f in factors:
+        if f.dtype != torch.float32 or not f.is_contiguous() or f.dim() != 2:
+            raise ValueError("factors must be contiguous 2-D float32 tensors")
+    R = factors[0].shape[1]
+    arr = (ctypes.c_void_p * len(factors))(*[f.data_ptr() for f in factors])
+    if storage not in ("fp32", "bf16"):
+        raise ValueError("storage must be 'fp32' or 'bf16'")
+    for m, f in enumerate(factors):
+        if f.shape[0] != t.dims[m] or f.shape[1] != R:
+            raise ValueError(f"factor {m} must be {t.dims[m]} x {R}")
+    opts = _CPALSOpts(int(max_iters), float(tol), BF16 if storage == "bf16" else F32)
+    fits = np.zeros(int(max_iters), dtype=np.float64)
+    rep = _CPALSReport()
+    _check(lib().blco_cp_als(t.handle, arr, R, ctypes.byref(opts), fits.ctypes.data,
+                             ctypes.byref(rep), _stream(stream)))
+    return fits[:rep.iters].tolist(), {"iters": rep.iters, "pinv_fallbacks": rep.pinv_fallbacks}
 
 
 class CPLoss(torch.autograd.Function):
