@@ -15,6 +15,7 @@ Other legs (``--workload``):
            streamed under an 8 GB device budget; copy/compute overlap reported;
   cpgrad4  sparse CP loss + gradient step, 4-mode 2^20 x 2^18 x 2^16 x 2^12,
            80M non-zeros holding a planted rank-8 model plus noise, R = 32;
+  cpals4   CP-ALS (Algorithm 1) iterations on the cpgrad4 tensor, R = --rank;
   uniform3 the zipf3 shape with uniform indices;
   short4   4-mode 2^21 x 2^17 x 24 x 168, 50M non-zeros, R = 32: the two short
            modes take hierarchical conflict resolution (Section 5.3 heuristic),
@@ -416,6 +417,67 @@ def leg_cpgrad(args, torch, blco, synth, w):
     return res
 
 
+def leg_cpals(args, torch, blco, synth, w):
+    """CP-ALS (Algorithm 1) on the planted-model tensor of the CP-gradient recipe."""
+    dev = torch.device("cuda:0")
+    timer = Timer(torch)
+    t0 = time.time()
+    coords, _ = synth.workload_tensor(w, nnz=args.nnz, log=log)
+    nnz = len(coords[0])
+    G = [synth.draw_u01_matrix(d, 8, w.seed, synth.S_TRUTH + m) for m, d in enumerate(w.dims)]
+    vals = planted_values(torch, coords, G, 0.01, w.seed, synth)
+    log(f"generated {nnz} non-zeros with planted values in {time.time() - t0:.1f}s")
+    T = blco.build(coords, vals, w.dims)
+    N = len(w.dims)
+    R = args.rank
+    A = [synth.draw_u01_matrix(d, R, w.seed, synth.S_FACTOR + m).astype(np.float32)
+         for m, d in enumerate(w.dims)]
+    F = [torch.from_numpy(a).to(dev) for a in A]
+    outs = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in w.dims]
+    mk = [timer(lambda n=n: blco.mttkrp_acc(T, n, F, outs[n]), args.steps) for n in range(N)]
+    blco.cp_als(T, [f.clone() for f in F], max_iters=max(args.warmup, 1), tol=-1.0)
+    torch.cuda.synchronize()
+    iters = max(args.steps, 2)
+    Fw = [f.clone() for f in F]
+    torch.cuda.synchronize()
+    t0 = time.time()
+    fits, rep = blco.cp_als(T, Fw, max_iters=iters, tol=-1.0)
+    torch.cuda.synchronize()
+    ms_iter = (time.time() - t0) * 1e3 / rep["iters"]
+    log(f"CP-ALS R={R}: {ms_iter:.2f} ms per iteration, MTTKRP kernels {[round(x, 3) for x in mk]} "
+        f"ms, fits {[round(f, 5) for f in fits]}")
+    res = base_result(args, w, nnz, nnz * N / (ms_iter * 1e-3) / 1e9, ms_iter)
+    res["metric"] = "CP-ALS iteration Gnnz/s (N MTTKRPs + Gram, V pseudo-inverse, M V^+, fit)"
+    res["config"].update({"rank": R, "model_rank": 8, "noise_sigma": 0.01, "iterations": iters})
+    per_nnz = 12 + (N - 1) * R * 4
+    avg = float(np.mean(mk))
+    res["roofline"] = {
+        "bound": "hbm", "achieved": nnz * per_nnz / (avg * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": nnz * per_nnz / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+        "kernel": [short_kernel_name(R, N) if T.resolution(n, R) == "hierarchical"
+                   else win_kernel_name(R, N) for n in range(N)],
+        "bytes_per_nnz": per_nnz, "avg_kernel_ms": avg,
+        "model": "requested bytes 12 + (N-1)*R*4 per non-zero of the MTTKRP kernels",
+    }
+    res["mttkrp_kernel_ms"] = mk
+    res["mttkrp_share_of_iteration"] = sum(mk) / ms_iter
+    res["fits"] = fits
+    res["pinv_fallbacks"] = rep["pinv_fallbacks"]
+    res["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        from oracle import cpals
+
+        S = min(args.cpu_sample_nnz, nnz)
+        t0 = time.time()
+        _, fw = cpals.cp_als([c[:S] for c in coords], vals[:S], [a.astype(np.float64) for a in A],
+                             w.dims, max_iters=1)
+        dt = time.time() - t0
+        res["cpu_baseline"] = {"value": S * N / dt / 1e9, "unit": "Gnnz/s", "cores": 1,
+                               "kind": "oracle", "sample": f"one CP-ALS iteration over the first "
+                               f"{S} non-zeros, fp64, single thread, {dt:.1f}s"}
+    return res
+
+
 def win_kernel_name(R, N, ft="float", big=False):
     """Template name of the window MTTKRP kernel the library launches for rank R."""
     lpn, rpl = (16, 1) if R <= 16 else (16, 2) if R <= 32 else (16, 4) if R <= 64 else (64, 2)
@@ -528,14 +590,16 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zipf3",
-                    choices=["zipf3", "uniform3", "zipf4", "oom3", "cpgrad4", "short4", "small"])
+                    choices=["zipf3", "uniform3", "zipf4", "oom3", "cpgrad4", "cpals4", "short4",
+                             "small"])
     ap.add_argument("--nnz", type=int, default=None, help="shrink the workload (same recipe)")
     ap.add_argument("--budget", type=int, default=None, help="device budget for oom3 (bytes)")
     ap.add_argument("--cpu-sample-nnz", type=int, default=4_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--resolution-sweep", action="store_true",
                     help="time both conflict-resolution mechanisms over short-mode lengths")
-    ap.add_argument("--rank", type=int, default=32, help="rank of --resolution-sweep")
+    ap.add_argument("--rank", type=int, default=32,
+                    help="rank of --resolution-sweep and of the cpals4 leg")
     ap.add_argument("--calibrate-copy-bytes", type=int, default=0,
                     help="also run one plain device-to-device copy of this many bytes "
                          "(the reference for HBM traffic counters)")
@@ -562,11 +626,13 @@ def main():
     if args.resolution_sweep:
         print(json.dumps(resolution_sweep(args, torch, blco, synth)), flush=True)
         return
-    w = synth.WORKLOADS[args.workload]
+    w = synth.WORKLOADS.get(args.workload)
     if args.workload == "oom3":
         res = leg_oom(args, torch, blco, synth, w)
     elif args.workload == "cpgrad4":
         res = leg_cpgrad(args, torch, blco, synth, w)
+    elif args.workload == "cpals4":
+        res = leg_cpals(args, torch, blco, synth, synth.WORKLOADS["cpgrad4"])
     else:
         res = leg_inmemory(args, torch, blco, synth, w)
     print(json.dumps(res), flush=True)

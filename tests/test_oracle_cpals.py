@@ -119,3 +119,14 @@ def test_singular_v_gives_minimum_norm_solution():
     np.testing.assert_allclose(M[:, 0], M[:, 1], rtol=1e-12)
     np.testing.assert_allclose(An[:, 0], An[:, 1], rtol=1e-10, atol=1e-12)
     np.testing.assert_allclose(An @ V, M, rtol=1e-10, atol=1e-10)
+
+
+def test_one_mode_update_is_the_data():
+    # N = 1: V is the empty Hadamard product (all ones); with R = 1 one update
+    # returns the vector of values itself
+    x = np.array([3.0, 0.0, -1.5, 2.0])
+    coords = [np.array([0, 2, 3], np.uint32)]
+    vals = x[[0, 2, 3]]
+    A1, M, V = cpals.als_update(coords, vals, [np.ones((4, 1))], 0, (4,))
+    np.testing.assert_array_equal(V, [[1.0]])
+    np.testing.assert_allclose(A1[:, 0], x, rtol=0, atol=0)
