@@ -71,6 +71,7 @@ typedef struct {
   int key_bits;          /* target integer width of a key, 1..64 (default 64), Section 4.2 */
   int64_t max_block_nnz; /* cap on the non-zeros of a block, >= 1 (default 2^27), Section 4.2 */
   int placement;         /* BLCO_PLACE_* (default BLCO_PLACE_DEVICE) */
+  int64_t hot_min_count; /* frequent-row threshold (0: default 2048; < 0: none), see blco_build */
 } blco_build_opts;
 
 typedef struct {
@@ -95,6 +96,7 @@ typedef struct {
   double stream_copy_ms;     /* last streaming call: host-to-device copy time, summed over chunks */
   double stream_kernel_ms;   /* last streaming call: MTTKRP kernel time, summed over chunks */
   double stream_total_ms;    /* last streaming call: first copy start to last kernel end */
+  int hot_rows[BLCO_MAX_MODES]; /* frequent rows recorded per mode (see blco_build) */
 } blco_info_t;
 
 /*
@@ -105,7 +107,12 @@ typedef struct {
  * Steps: ALTO linearization of every coordinate (Section 4.1), a stable sort
  * along the encoding line, re-encoding into per-mode bit fields decoded by
  * shift and mask (Figure 6b), blocks on the uppermost T - K bits, split to
- * at most max_block_nnz non-zeros (Section 4.2).  The inputs are copied: the
+ * at most max_block_nnz non-zeros (Section 4.2).  Also records, per mode of
+ * at most 2^26 rows, up to 256 frequent rows (estimated from at most 2^22
+ * evenly spaced non-zeros; at least hot_min_count non-zeros each, most
+ * frequent first): the register-based MTTKRP sums their updates per
+ * workgroup in LDS instead of once per window (not a mode-specific copy:
+ * 1 KiB per mode).  The inputs are copied: the
  * caller may free them on return.  Duplicate coordinates are kept (their
  * terms add up).  On success *out owns every buffer; release it with
  * blco_free.  Errors: EINVAL, ERANGE, EUNSUPPORTED, ENOMEM, EDEVICE.

@@ -47,7 +47,7 @@ class BLCOError(RuntimeError):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("key_bits", ctypes.c_int), ("max_block_nnz", ctypes.c_int64),
-                ("placement", ctypes.c_int)]
+                ("placement", ctypes.c_int), ("hot_min_count", ctypes.c_int64)]
 
 
 class _CPALSOpts(ctypes.Structure):
@@ -68,7 +68,8 @@ class _Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t), ("host_bytes", ctypes.c_size_t),
                 ("stream_peak_bytes", ctypes.c_size_t), ("stream_chunks", ctypes.c_int64),
                 ("stream_chunk_nnz", ctypes.c_int64), ("stream_copy_ms", ctypes.c_double),
-                ("stream_kernel_ms", ctypes.c_double), ("stream_total_ms", ctypes.c_double)]
+                ("stream_kernel_ms", ctypes.c_double), ("stream_total_ms", ctypes.c_double),
+                ("hot_rows", ctypes.c_int * MAX_MODES)]
 
 
 def library_path() -> str:
@@ -144,7 +145,8 @@ class BLCOTensor:
                     device_bytes=inf.device_bytes, host_bytes=inf.host_bytes,
                     stream_peak_bytes=inf.stream_peak_bytes, stream_chunks=inf.stream_chunks,
                     stream_chunk_nnz=inf.stream_chunk_nnz, stream_copy_ms=inf.stream_copy_ms,
-                    stream_kernel_ms=inf.stream_kernel_ms, stream_total_ms=inf.stream_total_ms)
+                    stream_kernel_ms=inf.stream_kernel_ms, stream_total_ms=inf.stream_total_ms,
+                    hot_rows=list(inf.hot_rows[:N]))
 
     @property
     def nnz(self) -> int:
@@ -191,8 +193,12 @@ class BLCOTensor:
             pass
 
 
-def build(coords, values, dims, key_bits=64, max_block_nnz=1 << 27, placement="device"):
-    """Build a BLCO tensor from 0-based COO coordinates (list of N integer arrays) and values."""
+def build(coords, values, dims, key_bits=64, max_block_nnz=1 << 27, placement="device",
+          hot_min_count=0):
+    """Build a BLCO tensor from 0-based COO coordinates (list of N integer arrays) and values.
+
+    hot_min_count: non-zeros a row needs to count as frequent (0: the library's
+    default; negative: no frequent rows)."""
     N = len(dims)
     cs = [np.ascontiguousarray(c, dtype=np.uint32) for c in coords]
     if len(cs) != N:
@@ -200,7 +206,7 @@ def build(coords, values, dims, key_bits=64, max_block_nnz=1 << 27, placement="d
     v = np.ascontiguousarray(values, dtype=np.float32)
     d = np.ascontiguousarray(dims, dtype=np.uint64)
     arr = (ctypes.c_void_p * N)(*[c.ctypes.data for c in cs])
-    opts = _Opts(key_bits, max_block_nnz, PLACEMENTS[placement])
+    opts = _Opts(key_bits, max_block_nnz, PLACEMENTS[placement], int(hot_min_count))
     h = ctypes.c_void_p()
     _check(lib().blco_build(N, d.ctypes.data, len(v), arr, v.ctypes.data, ctypes.byref(opts),
                             ctypes.byref(h)))

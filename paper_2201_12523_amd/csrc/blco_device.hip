@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "blco_internal.h"
 #include "blco_kernels.h"
@@ -240,63 +241,6 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tile(KParams p) {
   }
 }
 
-// Exchange of one value between lanes `stride` apart across a workgroup:
-// within a wave by a cross-lane permute, across waves through LDS.
-template <int STRIDE>
-__device__ __forceinline__ uint32_t xchg32(uint32_t v, int tid, uint32_t* lds) {
-  if constexpr (STRIDE < 64) {
-    return (uint32_t)__shfl_xor((int)v, STRIDE);
-  } else {
-    lds[tid] = v;
-    __syncthreads();
-    uint32_t o = lds[tid ^ STRIDE];
-    __syncthreads();
-    return o;
-  }
-}
-
-template <int STRIDE>
-__device__ __forceinline__ uint64_t xchg64(uint64_t v, int tid, uint64_t* lds) {
-  if constexpr (STRIDE < 64) {
-    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, STRIDE);
-    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), STRIDE);
-    return ((uint64_t)hi << 32) | lo;
-  } else {
-    lds[tid] = v;
-    __syncthreads();
-    uint64_t o = lds[tid ^ STRIDE];
-    __syncthreads();
-    return o;
-  }
-}
-
-template <typename K, int SIZE, int STRIDE>
-__device__ __forceinline__ K bitonic_step(K v, int tid, K* lds) {
-  K o;
-  if constexpr (sizeof(K) == 4) o = (K)xchg32<STRIDE>((uint32_t)v, tid, (uint32_t*)lds);
-  else o = (K)xchg64<STRIDE>((uint64_t)v, tid, (uint64_t*)lds);
-  const bool asc = (tid & SIZE) == 0;
-  const bool lower = (tid & STRIDE) == 0;
-  const K mn = v < o ? v : o;
-  const K mx = v < o ? o : v;
-  return (asc == lower) ? mn : mx;
-}
-
-template <typename K, int SIZE, int STRIDE>
-__device__ __forceinline__ K bitonic_merge(K v, int tid, K* lds) {
-  v = bitonic_step<K, SIZE, STRIDE>(v, tid, lds);
-  if constexpr (STRIDE > 1) v = bitonic_merge<K, SIZE, STRIDE / 2>(v, tid, lds);
-  return v;
-}
-
-// Ascending bitonic sort of one key per thread over a workgroup of WIN threads.
-template <typename K, int WIN, int SIZE = 2>
-__device__ __forceinline__ K block_sort(K v, int tid, K* lds) {
-  v = bitonic_merge<K, SIZE, SIZE / 2>(v, tid, lds);
-  if constexpr (SIZE < WIN) v = block_sort<K, WIN, SIZE * 2>(v, tid, lds);
-  return v;
-}
-
 constexpr int kWin = 1024;     // non-zeros per window (one per thread of the workgroup)
 constexpr int kWinBits = 10;
 #ifndef BLCO_WIN_U
@@ -308,9 +252,6 @@ constexpr int kWinBits = 10;
 #define BLCO_WIN_OCC 8
 #endif
 
-#ifndef BLCO_WIN_BITONIC
-#define BLCO_WIN_BITONIC 0
-#endif
 constexpr int kBucketBits = 12;
 constexpr int kBuckets = 1 << kBucketBits;   // hash buckets per window
 
@@ -370,144 +311,96 @@ __device__ __forceinline__ float ld_buf<uint16_t>(__amdgpu_buffer_rsrc_t r, uint
   return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0) << 16);
 }
 
-// BLCO MTTKRP with register-based conflict resolution over a window of 1024
-// consecutive non-zeros per workgroup (Sections 5.1-5.2).
-//   processing: one non-zero per thread is loaded and decoded by shift and
-//     mask; the workgroup sorts the window by target index (bitonic network:
-//     in-wave stages by cross-lane permutes, cross-wave stages through LDS),
-//     so each target's terms form one segment, and writes one record per
-//     sorted position: value, byte offsets of the other modes' factor rows,
-//     target;
-//   computing: groups of LPN lanes (one rank per lane) walk LPN consecutive
-//     sorted positions each, gathering factor rows with buffer loads and
-//     accumulating the scaled Hadamard product in a register; a segment that
-//     ends inside the group is added to the output with one atomic per rank;
-//     a segment that crosses into later groups is completed by the group it
-//     started in, from partial sums the later groups leave in LDS.
-// Every target therefore costs one global atomic per (window, rank).  On
-// MI355X same-address atomics serialise (about 32 ns each), so merging the
-// whole window bounds the atomic chains of frequent output rows.
+// Frequent-row lookup of the window kernel: open addressing over kHotSlots
+// LDS slots holding (row, stash index); at most half full.
+constexpr int kHotSlots = 2 * blco::kHotMax;
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;
+constexpr uint32_t kHotFlag = 0x80000000u;   // record target field: stash index follows
+
+__device__ __forceinline__ uint32_t hot_hash(uint32_t row) {
+  return (row * 0x9E3779B1u) >> (32 - 9);   // 9 bits: kHotSlots = 512
+}
+
+__device__ __forceinline__ int hot_lookup(const uint32_t* keys, const uint32_t* idx, uint32_t row) {
+  uint32_t h = hot_hash(row);
+  for (int probe = 0; probe < kHotSlots; ++probe) {
+    const uint32_t k = keys[h];
+    if (k == row) return (int)idx[h];
+    if (k == kNoRow) return -1;
+    h = (h + 1) & (kHotSlots - 1);
+  }
+  return -1;
+}
+
+// BLCO MTTKRP with register-based conflict resolution (Sections 5.1-5.2) over
+// windows of 1024 consecutive non-zeros; persistent workgroups take windows
+// blockIdx.x, blockIdx.x + gridDim.x, ...
+//   processing: one non-zero per thread is loaded (the next window's load is
+//     issued before the current walk) and decoded by shift and mask; the
+//     window is grouped by target with a counting sort (LDS histogram with
+//     atomic ranks, exclusive scan, scatter) on a hash of the target, so each
+//     target's terms form one contiguous segment, and each grouped position
+//     gets a record: byte offsets of the other modes' factor rows, target,
+//     value;
+//   computing: groups of LPN lanes (RPL ranks per lane) walk LPN consecutive
+//     grouped positions each, gathering factor rows with buffer loads and
+//     summing the scaled Hadamard products in registers; a segment that ends
+//     inside the group is flushed once per rank; a segment that crosses into
+//     later groups is completed by the group it started in, from partial sums
+//     the later groups leave in LDS.
+// A flush is a device-scope atomic into the output, which MI355X performs at
+// the memory side (same-address updates serialise at about 32 ns), except for
+// the mode's frequent rows (found at build time): those get buckets of their
+// own, so each has exactly one segment per window, and its flush is a plain
+// add into the workgroup's LDS stash row; the stash goes to the output with
+// one atomic per (row, rank) when the workgroup ends.
 template <int LPN, int RPL, typename FT, int N, bool BIG>
 __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   constexpr int G = kWin / LPN;                 // groups of LPN lanes
-  constexpr int PPG = kWin / G;                 // sorted positions per group (= LPN)
+  constexpr int PPG = kWin / G;                 // grouped positions per group (= LPN)
   constexpr int U = PPG < (BLCO_WIN_U / RPL) ? PPG : (BLCO_WIN_U / RPL);
   constexpr int NF = N + 1;                     // record fields
   constexpr int NP = NF <= 4 ? 4 : ((NF + 1) / 2) * 2;
-  constexpr int NS = NP > NF ? NP : NF;         // staging/record region, u32 per position
-  __shared__ __align__(16) uint32_t s_rec[kWin * NS];  // records by grouped position
+  __shared__ __align__(16) uint32_t s_rec[kWin * NP];  // records by grouped position
   __shared__ uint64_t s_end[kWin / 64];
   __shared__ float s_head[kWin * RPL];
-#if BLCO_WIN_BITONIC
-  __shared__ uint64_t s_key[kWin];
-#else
   __shared__ uint32_t s_hist[kBuckets];
   __shared__ uint32_t s_wsum[kWin / 64];
-#endif
+  extern __shared__ __align__(16) unsigned char s_dyn_win[];
+  const int K = p.nhot;                                   // frequent rows in the stash
+  const int R = p.R;
+  float* s_stash = reinterpret_cast<float*>(s_dyn_win);   // K x R
+  uint32_t* s_hkey = reinterpret_cast<uint32_t*>(s_stash + (size_t)K * R);
+  uint32_t* s_hidx = s_hkey + kHotSlots;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  int64_t win = blockIdx.x;
-  if (p.xcd_remap) {
-    const int64_t per = gridDim.x / 8;
-    if (win < per * 8) win = (win % 8) * per + win / 8;
+  const int64_t nwin = (p.n + kWin - 1) / kWin;
+  if (K > 0) {
+    for (int i = tid; i < K * R; i += kWin) s_stash[i] = 0.f;
+    for (int i = tid; i < kHotSlots; i += kWin) s_hkey[i] = kNoRow;
+    __syncthreads();
+    if (tid < K) {
+      const uint32_t row = p.hot[tid];
+      uint32_t h = hot_hash(row);
+      for (int probe = 0; probe < kHotSlots; ++probe) {
+        if (atomicCAS(&s_hkey[h], kNoRow, row) == kNoRow) {
+          s_hidx[h] = (uint32_t)tid;
+          break;
+        }
+        h = (h + 1) & (kHotSlots - 1);
+      }
+    }
   }
-  const int64_t k0 = win * kWin;
-  if (k0 >= p.n) return;
-  const int nvalid = (int)min((int64_t)kWin, p.n - k0);
-  const bool valid = tid < nvalid;
-
-  // ---- processing: load, decode, stage by window position
-  uint32_t c[N];
-  float x = 0.f;
-  if (valid) {
-    const uint64_t key = p.keys[k0 + tid];
-    x = p.vals[k0 + tid];
-    decode<N>(p, key, p.base + k0 + tid, c);
-  } else {
-#pragma unroll
-    for (int m = 0; m < N; ++m) c[m] = 0;
-  }
-  uint32_t tgt = 0;
-#pragma unroll
-  for (int m = 0; m < N; ++m)
-    if (m == p.mode) tgt = c[m];
-#if BLCO_WIN_BITONIC
-#pragma unroll
-  for (int m = 0; m < N; ++m) s_rec[m * kWin + tid] = c[m];
-  s_rec[N * kWin + tid] = __float_as_uint(x);
-  // ---- sort the window by target
-  uint64_t sk;
-  if (!p.wide) {
-    uint32_t v = valid ? ((tgt << kWinBits) | (uint32_t)tid) : 0xFFFFFFFFu;
-    v = block_sort<uint32_t, kWin>(v, tid, (uint32_t*)s_key);
-    sk = v;
-  } else {
-    uint64_t v = valid ? (((uint64_t)tgt << kWinBits) | (uint64_t)tid) : ~0ULL;
-    sk = block_sort<uint64_t, kWin>(v, tid, s_key);
-  }
-  s_key[tid] = sk;
-  __syncthreads();
-  const bool end = (tid < nvalid) &&
-                   (tid == nvalid - 1 || (s_key[tid + 1] >> kWinBits) != (sk >> kWinBits));
-  const uint64_t em = __ballot(end);
-  if (lane == 0) s_end[tid >> 6] = em;
-  // gather this sorted position's record from the staging area (fields as below)
-  const int src = (int)(sk & (kWin - 1));
-  uint32_t rec[NF];
-#pragma unroll
-  for (int j = 0; j + 1 < N; ++j) {
-    const uint32_t cj = s_rec[((j < p.mode) ? j : j + 1) * kWin + src];
-    rec[j] = BIG ? cj : cj * p.rowbytes;
-  }
-  rec[N - 1] = s_rec[p.mode * kWin + src];
-  rec[N] = s_rec[N * kWin + src];
-  __syncthreads();
-#pragma unroll
-  for (int f = 0; f < NF; ++f) s_rec[tid * NP + f] = rec[f];
-  __syncthreads();
-#else
-  // ---- group the window by target: counting sort on a hash of the target.
-  // Equal targets land in one bucket, so they become one contiguous run; two
-  // targets sharing a bucket may interleave, which only splits a segment.
-  for (int i = tid; i < kBuckets; i += kWin) s_hist[i] = 0;
-  __syncthreads();
-  const uint32_t bkt = (tgt * 0x9E3779B1u) >> (32 - kBucketBits);
-  uint32_t rank = 0;
-  if (valid) rank = atomicAdd(&s_hist[bkt], 1u);
-  __syncthreads();
-  block_exclusive_scan<kBuckets, kWin>(s_hist, tid, s_wsum);
-  // record of this non-zero at its grouped position: fields 0..N-2 hold the byte
-  // offsets (row indices when BIG) of the factor rows of the other modes in
-  // ascending mode order, field N-1 the target row, field N the value; padding
-  // lanes keep their own (trailing) positions
-  const int pos = valid ? (int)(s_hist[bkt] + rank) : tid;
-#pragma unroll
-  for (int j = 0; j + 1 < N; ++j) {
-    const uint32_t cj = (j < p.mode) ? c[j] : c[j + 1];
-    s_rec[pos * NP + j] = BIG ? cj : cj * p.rowbytes;
-  }
-  s_rec[pos * NP + N - 1] = tgt;
-  s_rec[pos * NP + N] = __float_as_uint(x);
-  __syncthreads();
+  // the first window's non-zero of this thread
+  uint64_t nkey = 0;
+  float nx = 0.f;
   {
-    const uint32_t t0 = s_rec[tid * NP + N - 1];
-    const bool end = (tid < nvalid) && (tid == nvalid - 1 || s_rec[(tid + 1) * NP + N - 1] != t0);
-    const uint64_t em = __ballot(end);
-    if (lane == 0) s_end[tid >> 6] = em;
+    const int64_t k = (int64_t)blockIdx.x * kWin + tid;
+    if ((int64_t)blockIdx.x < nwin && k < p.n) {
+      nkey = p.keys[k];
+      nx = p.vals[k];
+    }
   }
-  __syncthreads();
-#endif
-
-  // ---- computing: LPN lanes per group, RPL ranks per lane (lane j holds ranks
-  // j, j + LPN, ...), each group walking LPN consecutive grouped positions
-  const int g = tid / LPN;
-  const int rl = tid % LPN;
-  const int p0 = g * PPG;
-  const uint64_t endw = s_end[p0 >> 6] >> (p0 & 63);
-  const uint64_t gmask = PPG >= 64 ? ~0ULL : ((1ULL << PPG) - 1);
-  const bool starts_before =
-      p0 > 0 && p0 < nvalid && !((s_end[(p0 - 1) >> 6] >> ((p0 - 1) & 63)) & 1);
-  const bool can_carry = p0 + PPG <= nvalid;
   constexpr int NO = N > 1 ? N - 1 : 1;          // other modes
   __amdgpu_buffer_rsrc_t rs[NO];
   const void* ap[NO];
@@ -519,83 +412,184 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
                                               (int)kBufFlags);
   }
   const float scale = term_scale(p);
-  const int R = p.R;
-  for (int r0 = 0; r0 < R; r0 += LPN * RPL) {
-    bool ract[RPL];
-    uint32_t loff[RPL];
-    float acc[RPL], carry[RPL];
+  const int g = tid / LPN;
+  const int rl = tid % LPN;
+  const int p0 = g * PPG;
+  const uint64_t gmask = PPG >= 64 ? ~0ULL : ((1ULL << PPG) - 1);
+
+  for (int64_t win = blockIdx.x; win < nwin; win += gridDim.x) {
+    const int64_t k0 = win * kWin;
+    const int nvalid = (int)min((int64_t)kWin, p.n - k0);
+    const bool valid = tid < nvalid;
+
+    // ---- processing: decode, group by target
+    uint32_t c[N];
+    const float x = valid ? nx : 0.f;
+    if (valid) {
+      decode<N>(p, nkey, p.base + k0 + tid, c);
+    } else {
 #pragma unroll
-    for (int k = 0; k < RPL; ++k) {
-      const int r = r0 + rl + k * LPN;
-      ract[k] = r < R;
-      loff[k] = (uint32_t)(ract[k] ? r : 0) * (uint32_t)sizeof(FT);
-      acc[k] = 0.f;
-      carry[k] = 0.f;
+      for (int m = 0; m < N; ++m) c[m] = 0;
     }
-    bool first = true, has_carry = false;
-    for (int q0 = 0; q0 < PPG; q0 += U) {
-      float pr[U][RPL];
+    uint32_t tgt = 0;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t* e = &s_rec[(p0 + q0 + u) * NP];
-        const float xv = __uint_as_float(e[N]);
+    for (int m = 0; m < N; ++m)
+      if (m == p.mode) tgt = c[m];
+    for (int i = tid; i < kBuckets; i += kWin) s_hist[i] = 0;
+    __syncthreads();   // also: the stash lookup is built, the previous window is done
+    // counting sort on a hash of the target; a frequent row has bucket = its
+    // stash index, the other targets share the remaining buckets (two targets
+    // sharing a bucket may interleave, which only splits a segment)
+    uint32_t tfield = tgt, bkt;
+    const int hs = (K > 0 && valid) ? hot_lookup(s_hkey, s_hidx, tgt) : -1;
+    if (hs >= 0) {
+      bkt = (uint32_t)hs;
+      tfield = kHotFlag | (uint32_t)hs;
+    } else {
+      const uint32_t h = tgt * 0x9E3779B1u;
+      bkt = (uint32_t)K + (uint32_t)(((uint64_t)h * (uint32_t)(kBuckets - K)) >> 32);
+    }
+    uint32_t rank = 0;
+    if (valid) rank = atomicAdd(&s_hist[bkt], 1u);
+    __syncthreads();
+    block_exclusive_scan<kBuckets, kWin>(s_hist, tid, s_wsum);
+    // record at the grouped position: fields 0..N-2 the byte offsets (row
+    // indices when BIG) of the other modes' factor rows in ascending mode
+    // order, field N-1 the target field, field N the value; padding lanes
+    // keep their own (trailing) positions
+    const int pos = valid ? (int)(s_hist[bkt] + rank) : tid;
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) pr[u][k] = xv;
-#pragma unroll
-        for (int j = 0; j + 1 < N; ++j) {
-          const uint32_t f = e[j];
-          if constexpr (BIG) {
-            const FT* rowp = static_cast<const FT*>(ap[j]) + (size_t)f * R;
-#pragma unroll
-            for (int k = 0; k < RPL; ++k)
-              pr[u][k] *= ld_factor<FT>(rowp, (size_t)(loff[k] / sizeof(FT)));
-          } else {
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) pr[u][k] *= ld_buf<FT>(rs[j], f + loff[k]);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int q = q0 + u;
-#pragma unroll
-        for (int k = 0; k < RPL; ++k) acc[k] += pr[u][k];
-        const bool seg_end = (endw >> q) & 1;
-        if (seg_end || (q == PPG - 1 && can_carry)) {
-          if (first && starts_before) {
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) s_head[tid * RPL + k] = acc[k];
-          } else if (seg_end) {
-            const size_t row = (size_t)seg_target(s_rec, (p0 + q) * NP, p.mode, N) * R;
-#pragma unroll
-            for (int k = 0; k < RPL; ++k)
-              if (ract[k]) unsafeAtomicAdd(p.out + row + r0 + rl + k * LPN, acc[k] * scale);
-          } else {
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) carry[k] = acc[k];
-            has_carry = true;
-          }
-#pragma unroll
-          for (int k = 0; k < RPL; ++k) acc[k] = 0.f;
-          first = false;
-        }
+    for (int j = 0; j + 1 < N; ++j) {
+      const uint32_t cj = (j < p.mode) ? c[j] : c[j + 1];
+      s_rec[pos * NP + j] = BIG ? cj : cj * p.rowbytes;
+    }
+    s_rec[pos * NP + N - 1] = tfield;
+    s_rec[pos * NP + N] = __float_as_uint(x);
+    __syncthreads();
+    {
+      const uint32_t t0 = s_rec[tid * NP + N - 1];
+      const bool end = (tid < nvalid) && (tid == nvalid - 1 || s_rec[(tid + 1) * NP + N - 1] != t0);
+      const uint64_t em = __ballot(end);
+      if (lane == 0) s_end[tid >> 6] = em;
+    }
+    // the next window's non-zero, in flight during this walk
+    {
+      const int64_t k = (win + gridDim.x) * kWin + tid;
+      if (win + gridDim.x < nwin && k < p.n) {
+        nkey = p.keys[k];
+        nx = p.vals[k];
       }
     }
     __syncthreads();
-    if (has_carry) {
-      // this group owns a segment that continues into the next groups
-      for (int g2 = g + 1; g2 < G; ++g2) {
-        const int q2 = g2 * PPG;
+
+    // ---- computing: LPN lanes per group, RPL ranks per lane (lane j holds
+    // ranks j, j + LPN, ...), each group walking LPN consecutive positions
+    const uint64_t endw = s_end[p0 >> 6] >> (p0 & 63);
+    const bool starts_before =
+        p0 > 0 && p0 < nvalid && !((s_end[(p0 - 1) >> 6] >> ((p0 - 1) & 63)) & 1);
+    const bool can_carry = p0 + PPG <= nvalid;
+    for (int r0 = 0; r0 < R; r0 += LPN * RPL) {
+      bool ract[RPL];
+      uint32_t loff[RPL];
+      float acc[RPL], carry[RPL];
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) carry[k] += s_head[(g2 * LPN + rl) * RPL + k];
-        if ((s_end[q2 >> 6] >> (q2 & 63)) & gmask) break;
+      for (int k = 0; k < RPL; ++k) {
+        const int r = r0 + rl + k * LPN;
+        ract[k] = r < R;
+        loff[k] = (uint32_t)(ract[k] ? r : 0) * (uint32_t)sizeof(FT);
+        acc[k] = 0.f;
+        carry[k] = 0.f;
       }
-      const size_t row = (size_t)seg_target(s_rec, (p0 + PPG - 1) * NP, p.mode, N) * R;
+      bool first = true, has_carry = false;
+      for (int q0 = 0; q0 < PPG; q0 += U) {
+        float pr[U][RPL];
 #pragma unroll
-      for (int k = 0; k < RPL; ++k)
-        if (ract[k]) unsafeAtomicAdd(p.out + row + r0 + rl + k * LPN, carry[k] * scale);
+        for (int u = 0; u < U; ++u) {
+          const uint32_t* e = &s_rec[(p0 + q0 + u) * NP];
+          const float xv = __uint_as_float(e[N]);
+#pragma unroll
+          for (int k = 0; k < RPL; ++k) pr[u][k] = xv;
+#pragma unroll
+          for (int j = 0; j + 1 < N; ++j) {
+            const uint32_t f = e[j];
+            if constexpr (BIG) {
+              const FT* rowp = static_cast<const FT*>(ap[j]) + (size_t)f * R;
+#pragma unroll
+              for (int k = 0; k < RPL; ++k)
+                pr[u][k] *= ld_factor<FT>(rowp, (size_t)(loff[k] / sizeof(FT)));
+            } else {
+#pragma unroll
+              for (int k = 0; k < RPL; ++k) pr[u][k] *= ld_buf<FT>(rs[j], f + loff[k]);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = q0 + u;
+#pragma unroll
+          for (int k = 0; k < RPL; ++k) acc[k] += pr[u][k];
+          const bool seg_end = (endw >> q) & 1;
+          if (seg_end || (q == PPG - 1 && can_carry)) {
+            if (first && starts_before) {
+#pragma unroll
+              for (int k = 0; k < RPL; ++k) s_head[tid * RPL + k] = acc[k];
+            } else if (seg_end) {
+              const uint32_t tf = seg_target(s_rec, (p0 + q) * NP, p.mode, N);
+              if (K > 0 && (tf & kHotFlag)) {
+                float* srow = s_stash + (size_t)(tf & ~kHotFlag) * R + r0 + rl;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k)
+                  if (ract[k]) srow[k * LPN] += acc[k];
+              } else {
+                const size_t row = (size_t)tf * R;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k)
+                  if (ract[k]) unsafeAtomicAdd(p.out + row + r0 + rl + k * LPN, acc[k] * scale);
+              }
+            } else {
+#pragma unroll
+              for (int k = 0; k < RPL; ++k) carry[k] = acc[k];
+              has_carry = true;
+            }
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) acc[k] = 0.f;
+            first = false;
+          }
+        }
+      }
+      __syncthreads();
+      if (has_carry) {
+        // this group owns a segment that continues into the next groups
+        for (int g2 = g + 1; g2 < G; ++g2) {
+          const int q2 = g2 * PPG;
+#pragma unroll
+          for (int k = 0; k < RPL; ++k) carry[k] += s_head[(g2 * LPN + rl) * RPL + k];
+          if ((s_end[q2 >> 6] >> (q2 & 63)) & gmask) break;
+        }
+        const uint32_t tf = seg_target(s_rec, (p0 + PPG - 1) * NP, p.mode, N);
+        if (K > 0 && (tf & kHotFlag)) {
+          float* srow = s_stash + (size_t)(tf & ~kHotFlag) * R + r0 + rl;
+#pragma unroll
+          for (int k = 0; k < RPL; ++k)
+            if (ract[k]) srow[k * LPN] += carry[k];
+        } else {
+          const size_t row = (size_t)tf * R;
+#pragma unroll
+          for (int k = 0; k < RPL; ++k)
+            if (ract[k]) unsafeAtomicAdd(p.out + row + r0 + rl + k * LPN, carry[k] * scale);
+        }
+      }
+      __syncthreads();
     }
+  }
+  // ---- the stash of frequent rows: one atomic per (row, rank) that received a term
+  if (K > 0) {
     __syncthreads();
+    for (int i = tid; i < K * R; i += kWin) {
+      const float v = s_stash[i];
+      const int hr = i / R;
+      if (v != 0.f) unsafeAtomicAdd(p.out + (size_t)p.hot[hr] * R + (i - hr * R), v * scale);
+    }
   }
 }
 
@@ -1333,15 +1327,12 @@ static KernelFn select_loss(int N, int R, int fdt) {
 }
 
 // MTTKRP kernel variant, chosen once per process from BLCO_KERNEL:
-//   "win" (default): 1024-non-zero windows sorted per workgroup;
-//   "stash": persistent workgroups with an LDS segment stash;
+//   "win" (default): 1024-non-zero windows grouped per workgroup;
+//   "stash": persistent workgroups with a hashed LDS segment stash;
 //   "tile": 64-non-zero tiles sorted per wave;
 //   "naive": one thread and one atomic per (non-zero, rank).
-// BLCO_XCD_REMAP=1 gives consecutive windows to the same XCD (measured slower
-// on the Zipf workloads, so off by default).
 enum { kVarWin = 0, kVarStash = 1, kVarTile = 2, kVarNaive = 3 };
 static int g_variant = -1;
-static int g_xcd_remap = -1;
 
 // LDS bytes per workgroup for the stash kernel (BLCO_STASH_KB, default 64)
 static size_t stash_lds_budget() {
@@ -1365,8 +1356,6 @@ static int kernel_variant() {
     if (e && strcmp(e, "stash") == 0) g_variant = kVarStash;
     if (e && strcmp(e, "naive") == 0) g_variant = kVarNaive;
     if (e && strcmp(e, "tile") == 0) g_variant = kVarTile;
-    const char* x = getenv("BLCO_XCD_REMAP");
-    g_xcd_remap = (x && strcmp(x, "1") == 0) ? 1 : 0;
   }
   return g_variant;
 }
@@ -1388,6 +1377,39 @@ static int resolve(const blco_tensor* t, int mode, int rank, int* sw) {
     return BLCO_RES_HIERARCHICAL;
   }
   return (w && rows < (uint64_t)device_cus()) ? BLCO_RES_HIERARCHICAL : BLCO_RES_REGISTER;
+}
+
+// Static LDS bytes of a kernel, read once per kernel.
+static size_t kernel_static_lds(const void* f) {
+  static std::mutex mu;
+  static std::vector<std::pair<const void*, size_t>> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto& e : cache)
+    if (e.first == f) return e.second;
+  hipFuncAttributes a;
+  size_t v = 64 * 1024;   // unknown: assume no room
+  if (hipFuncGetAttributes(&a, f) == hipSuccess) v = a.sharedSizeBytes;
+  cache.push_back({f, v});
+  return v;
+}
+
+// LDS per window-kernel workgroup: half a CU's (two resident workgroups),
+// at most the per-workgroup limit; read once per device.
+static size_t win_lds_budget() {
+  static size_t cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64 * 1024;
+  if (!cached[dev]) {
+    int cu = 0, blk = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess || cu <= 0)
+      cu = 64 * 1024;
+    if (hipDeviceGetAttribute(&blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        blk <= 0)
+      blk = 64 * 1024;
+    cached[dev] = std::min<size_t>((size_t)cu / 2, (size_t)blk);
+  }
+  return cached[dev];
 }
 
 // ====================================================================== host runtime
@@ -1457,7 +1479,6 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
   p.scale = scale;
   p.scale_dev = scale_dev;
   int var = kernel_variant();
-  p.xcd_remap = g_xcd_remap;
   const size_t fsz = factor_elem_bytes(fdt);
   p.rowbytes = (uint32_t)((size_t)rank * fsz);
   // factors below 4 GiB are gathered with 32-bit byte offsets, larger ones
@@ -1526,10 +1547,23 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
     if (lds > 65536) HIPCHK(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(f, dim3((unsigned)nwg), dim3(kSB), lds, s, p, cfg);
   } else if (var == kVarWin) {
-    int64_t blocks = (n + kWin - 1) / kWin;
-    p.wide = t->lay.dims[mode] > (1ULL << (32 - kWinBits)) ? 1 : 0;
     KernelFn f = select_win(t->lay.N, rank, fdt, big);
-    hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(kWin), 0, s, p);
+    const int64_t nwin = (n + kWin - 1) / kWin;
+    // frequent rows of the target mode kept in the LDS stash: as many as fit
+    // beside the kernel's own LDS in one workgroup's share of a CU
+    int K = 0;
+    if (t->nhot[mode] > 0 && t->d_hot) {
+      const size_t fixed = kernel_static_lds((const void*)f) + 2 * (size_t)kHotSlots * 4;
+      const size_t budget = win_lds_budget();
+      if (budget > fixed)
+        K = (int)std::min<size_t>((size_t)t->nhot[mode], (budget - fixed) / ((size_t)rank * 4));
+    }
+    p.hot = t->d_hot + (size_t)mode * kHotMax;
+    p.nhot = K;
+    const size_t dyn = K > 0 ? (size_t)K * rank * 4 + 2 * (size_t)kHotSlots * 4 : 0;
+    // persistent: two resident workgroups per CU take the windows in turn
+    const int64_t grid = std::min<int64_t>(nwin, (int64_t)device_cus() * 2);
+    hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kWin), dyn, s, p);
   } else {
     int64_t tiles = (n + 63) / 64;
     int64_t blocks = (tiles + kWaves - 1) / kWaves;
@@ -1583,6 +1617,8 @@ static void release_device(blco_tensor* t) {
   if (t->d_run_base) (void)hipFree(t->d_run_base);
   if (t->d_tile_run) (void)hipFree(t->d_tile_run);
   if (t->d_partials) (void)hipFree(t->d_partials);
+  if (t->d_hot) (void)hipFree(t->d_hot);
+  t->d_hot = nullptr;
   t->d_keys = nullptr;
   t->d_vals = nullptr;
   t->d_run_start = nullptr;
@@ -1602,10 +1638,12 @@ extern "C" int blco_build(int nmodes, const uint64_t* dims, int64_t nnz,
   int key_bits = 64;
   int64_t cap = (int64_t)1 << 27;
   int placement = BLCO_PLACE_DEVICE;
+  int64_t hot_min = kHotMinCount;
   if (opts) {
     key_bits = opts->key_bits;
     cap = opts->max_block_nnz;
     placement = opts->placement;
+    if (opts->hot_min_count != 0) hot_min = opts->hot_min_count;
   }
   if (placement != BLCO_PLACE_DEVICE && placement != BLCO_PLACE_PINNED &&
       placement != BLCO_PLACE_HOST)
@@ -1624,6 +1662,7 @@ extern "C" int blco_build(int nmodes, const uint64_t* dims, int64_t nnz,
     delete t;
     return rc;
   }
+  find_hot_rows(coords, nnz, hot_min, t);
   if (placement == BLCO_PLACE_HOST) {
     *out = t;
     return BLCO_OK;
@@ -1642,6 +1681,7 @@ extern "C" int blco_build(int nmodes, const uint64_t* dims, int64_t nnz,
   if ((rc = upload(&t->d_run_start, t->run_start.data(), t->run_start.size(), &acc))) return fail(rc);
   if ((rc = upload(&t->d_run_base, t->run_base.data(), t->run_base.size(), &acc))) return fail(rc);
   if ((rc = upload(&t->d_tile_run, t->tile_run.data(), t->tile_run.size(), &acc))) return fail(rc);
+  if ((rc = upload(&t->d_hot, t->hot.data(), t->hot.size(), &acc))) return fail(rc);
   if (placement == BLCO_PLACE_DEVICE) {
     if ((rc = upload(&t->d_keys, t->h_keys, (size_t)nnz, &acc))) return fail(rc);
     if ((rc = upload(&t->d_vals, t->h_vals, (size_t)nnz, &acc))) return fail(rc);
@@ -1952,6 +1992,7 @@ extern "C" int blco_info(const blco_tensor* t, blco_info_t* info) {
     info->shift[m] = L.s[m];
     info->high[m] = L.h[m];
     info->dims[m] = L.dims[m];
+    info->hot_rows[m] = t->nhot[m];
   }
   info->nblocks = (int64_t)t->block_id.size();
   info->nruns = (int64_t)t->run_start.size() - 1;

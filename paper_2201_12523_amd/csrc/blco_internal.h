@@ -11,6 +11,8 @@
 namespace blco {
 
 constexpr int kTile = 64;  // non-zeros per wave tile (one per lane of a wave64)
+constexpr int kHotMax = 256;  // frequent rows kept per mode
+constexpr int64_t kHotMinCount = 2048;  // default: a frequent row holds at least this many non-zeros
 
 // The bit map of a tensor (Sections 4.1-4.2).
 struct Layout {
@@ -69,6 +71,11 @@ struct blco_tensor {
   int64_t stream_chunks = 0;
   int device = -1;
   int resolution = BLCO_RES_AUTO;   // conflict resolution (blco_set_resolution)
+  // frequent rows of each mode (kHotMax per mode, most frequent first, padded
+  // with 0xFFFFFFFF): the register-based kernel sums them per workgroup in LDS
+  std::vector<uint32_t> hot;         // N * kHotMax
+  int nhot[BLCO_MAX_MODES] = {};
+  uint32_t* d_hot = nullptr;
 };
 
 namespace blco {
@@ -85,6 +92,11 @@ typedef void (*HostFree)(void*);
 int host_build(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_t* const* coords,
                const float* values, int key_bits, int64_t max_block_nnz, HostAlloc alloc,
                HostFree release, blco_tensor* t);
+
+// Frequent rows of every mode (t->hot, t->nhot): rows counted over at most
+// 2^22 evenly spaced non-zeros, the kHotMax most frequent whose estimated count
+// reaches min_count (< 0: none).  Modes longer than 2^26 get none.
+void find_hot_rows(const uint32_t* const* coords, int64_t nnz, int64_t min_count, blco_tensor* t);
 
 void free_host_arrays(blco_tensor* t);
 

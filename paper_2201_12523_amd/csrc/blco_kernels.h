@@ -29,7 +29,8 @@ struct KParams {
   uint32_t shift[8];
   uint32_t mask[8];
   int wide;                   // target index too long for 32-bit sort keys
-  int xcd_remap;              // give consecutive windows to the same XCD
+  const uint32_t* hot;        // window kernel: frequent rows of the target mode
+  int nhot;                   // window kernel: frequent rows held in the LDS stash
   uint32_t short_rows;        // hierarchical kernel: target mode length
   int short_width;            // hierarchical kernel: ranks per slice
   uint32_t rowbytes;          // bytes of one factor row (R x element size)

@@ -65,11 +65,14 @@ def hierarchical_fits(t, n, R):
 
 
 def run_case(coords, vals, dims, R, modes=None, key_bits=64, cap=1 << 27, seed=0,
-             dtypes=("fp32",), label="", resolutions=("register", "hierarchical")):
+             dtypes=("fp32",), label="", resolutions=("register", "hierarchical", "frequent")):
     """Every mode under each conflict-resolution mechanism (hierarchical only where
-    the mode fits its LDS stash) against the oracle."""
+    the mode fits its LDS stash; "frequent": register-based with every mode's 256
+    most frequent rows summed in the workgroup stash) against the oracle."""
     say(f"case {label} dims={dims} nnz={len(vals)} R={R} key_bits={key_bits} cap={cap}")
-    t = blco.build(coords, vals, dims, key_bits=key_bits, max_block_nnz=cap)
+    t = blco.build(coords, vals, dims, key_bits=key_bits, max_block_nnz=cap, hot_min_count=-1)
+    th = blco.build(coords, vals, dims, key_bits=key_bits, max_block_nnz=cap, hot_min_count=1)
+    th.set_resolution("register")
     rng = np.random.default_rng(seed)
     A = [rng.standard_normal((d, R)).astype(np.float32) for d in dims]
     modes = range(len(dims)) if modes is None else modes
@@ -85,9 +88,12 @@ def run_case(coords, vals, dims, R, modes=None, key_bits=64, cap=1 << 27, seed=0
             for res in resolutions:
                 if res == "hierarchical" and not hierarchical_fits(t, n, R):
                     continue
-                t.set_resolution(res)
-                assert t.resolution(n, R) == res
-                out = blco.mttkrp(t, n, F)
+                if res == "frequent":
+                    out = blco.mttkrp(th, n, F)
+                else:
+                    t.set_resolution(res)
+                    assert t.resolution(n, R) == res
+                    out = blco.mttkrp(t, n, F)
                 torch.cuda.synchronize()
                 tag = f"{label} {dt} {res} mode {n}"
                 check_entries(out.cpu().numpy(), M, S, label=tag)
@@ -97,6 +103,7 @@ def run_case(coords, vals, dims, R, modes=None, key_bits=64, cap=1 << 27, seed=0
                     check_entries(out.cpu().numpy(), M32, S32, tol=bound,
                                   label=f"{tag} bf16-vs-fp32")
     t.free()
+    th.free()
 
 
 def test_figure4a_worked_example(fig4a):
@@ -425,3 +432,27 @@ def test_stream_all_modes_one_pass(placement):
     M, S = oracle.mttkrp(coords, vals, A, 1)
     check_entries(outs2[1].cpu().numpy(), M, S, label="stream_all subset")
     assert outs2[0] is None and outs2[2] is None
+
+
+def test_stream_with_frequent_rows():
+    # every chunk's workgroups sum the frequent rows in LDS and flush them at their end
+    rng = np.random.default_rng(77)
+    dims = (300, 200, 100)
+    nnz = 30_000
+    coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
+    coords[0][:9000] = rng.integers(0, 5, size=9000)
+    vals = rng.random(nnz).astype(np.float32)
+    R = 32
+    A = [rng.standard_normal((d, R)).astype(np.float32) for d in dims]
+    F = _dev_factors(A)
+    tp = blco.build(coords, vals, dims, placement="pinned", hot_min_count=1)
+    tp.set_resolution("register")
+    assert tp.info()["hot_rows"] == [256, 200, 100]
+    for n in range(3):
+        fixed = dims[n] * R * 4 + sum(dims[m] * R * 4 for m in range(3) if m != n)
+        fixed += tp.info()["device_bytes"]
+        out = blco.mttkrp_stream(tp, n, F, device_budget=fixed + 2 * 4000 * 12)
+        torch.cuda.synchronize()
+        assert tp.info()["stream_chunks"] >= 7
+        M, S = oracle.mttkrp(coords, vals, A, n)
+        check_entries(out.cpu().numpy(), M, S, label=f"stream frequent rows mode {n}")

@@ -162,3 +162,24 @@ def test_resolution_setting_and_heuristic():
     assert L.blco_resolution(t.handle, 0, 0, ctypes.byref(c)) == -1
     t.set_resolution("auto")
     assert L.blco_resolution(t.handle, 2, 8, ctypes.byref(c)) == 0 and c.value == 2
+
+
+def test_frequent_rows_recorded_at_build():
+    """Rows with at least hot_min_count non-zeros (at most 256 per mode, most
+    frequent first); none when disabled or for modes longer than 2^26."""
+    _lib_or_skip()
+    rng = np.random.default_rng(3)
+    nnz = 20_000
+    c0 = rng.integers(0, 1000, size=nnz).astype(np.uint32)
+    c0[:3000] = 7            # row 7: 3000+ non-zeros
+    c0[3000:5500] = 11       # row 11: 2500+
+    c1 = rng.integers(0, (1 << 27) + 5, size=nnz).astype(np.uint32)
+    c1[:4000] = 0
+    dims = (1000, (1 << 27) + 5)
+    vals = np.ones(nnz, np.float32)
+    t = blco.build([c0, c1], vals, dims, placement="host")
+    assert t.info()["hot_rows"] == [2, 0]           # default threshold 2048; mode 1 too long
+    t = blco.build([c0, c1], vals, dims, placement="host", hot_min_count=1)
+    assert t.info()["hot_rows"] == [256, 0]
+    t = blco.build([c0, c1], vals, dims, placement="host", hot_min_count=-1)
+    assert t.info()["hot_rows"] == [0, 0]
