@@ -213,8 +213,7 @@ def leg_inmemory(args, torch, blco, synth, w):
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
         "kernel": [short_kernel_name(R, N) if T.resolution(n, R) == "hierarchical"
-                   else win_kernel_name(R, N) for n in modes]
-        if any(T.resolution(n, R) == "hierarchical" for n in modes) else win_kernel_name(R, N),
+                   else win_kernel_name(R, N, stash=inf["hot_rows"][n] > 0) for n in modes],
         "bytes_per_nnz": per_nnz, "avg_kernel_ms": avg_kernel_ms,
         "model": "requested bytes 12 + (N-1)*R*s_f per non-zero (the paper's Vol); "
                  "frac above 1 means factor rows are served from cache",
@@ -478,10 +477,12 @@ def leg_cpals(args, torch, blco, synth, w):
     return res
 
 
-def win_kernel_name(R, N, ft="float", big=False):
-    """Template name of the window MTTKRP kernel the library launches for rank R."""
+def win_kernel_name(R, N, ft="float", big=False, stash=True):
+    """Template name of the window MTTKRP kernel the library launches for rank R
+    (stash: the mode has frequent rows held in LDS)."""
     lpn, rpl = (16, 1) if R <= 16 else (16, 2) if R <= 32 else (16, 4) if R <= 64 else (64, 2)
-    return f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {'true' if big else 'false'}>"
+    b = lambda v: "true" if v else "false"
+    return f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {b(big)}, {b(stash)}>"
 
 
 def short_kernel_name(R, N, ft="float", big=False):

@@ -71,7 +71,8 @@ typedef struct {
   int key_bits;          /* target integer width of a key, 1..64 (default 64), Section 4.2 */
   int64_t max_block_nnz; /* cap on the non-zeros of a block, >= 1 (default 2^27), Section 4.2 */
   int placement;         /* BLCO_PLACE_* (default BLCO_PLACE_DEVICE) */
-  int64_t hot_min_count; /* frequent-row threshold (0: default 2048; < 0: none), see blco_build */
+  int64_t hot_min_count; /* frequent-row threshold (0: default 2048; < 0: none; > 0: this one,
+                            and the stash is used whenever rows are found), see blco_build */
 } blco_build_opts;
 
 typedef struct {
@@ -112,7 +113,10 @@ typedef struct {
  * evenly spaced non-zeros; at least hot_min_count non-zeros each, most
  * frequent first): the register-based MTTKRP sums their updates per
  * workgroup in LDS instead of once per window (not a mode-specific copy:
- * 1 KiB per mode).  The inputs are copied: the
+ * 1 KiB per mode).  With the default threshold a mode uses them only when
+ * the most frequent row left out of the LDS stash is at most a quarter as
+ * frequent as the most frequent row; a threshold given in opts uses them
+ * whenever rows are found.  The inputs are copied: the
  * caller may free them on return.  Duplicate coordinates are kept (their
  * terms add up).  On success *out owns every buffer; release it with
  * blco_free.  Errors: EINVAL, ERANGE, EUNSUPPORTED, ENOMEM, EDEVICE.

@@ -242,6 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tile(KParams p) {
 }
 
 constexpr int kWin = 1024;     // non-zeros per window (one per thread of the workgroup)
+constexpr int kWinRounds = 4;  // dispatch rounds of the persistent window kernel
 constexpr int kWinBits = 10;
 #ifndef BLCO_WIN_U
 #define BLCO_WIN_U 8
@@ -334,7 +335,7 @@ __device__ __forceinline__ int hot_lookup(const uint32_t* keys, const uint32_t* 
 
 // BLCO MTTKRP with register-based conflict resolution (Sections 5.1-5.2) over
 // windows of 1024 consecutive non-zeros; persistent workgroups take windows
-// blockIdx.x, blockIdx.x + gridDim.x, ...
+// in turn (see below)
 //   processing: one non-zero per thread is loaded (the next window's load is
 //     issued before the current walk) and decoded by shift and mask; the
 //     window is grouped by target with a counting sort (LDS histogram with
@@ -354,7 +355,7 @@ __device__ __forceinline__ int hot_lookup(const uint32_t* keys, const uint32_t* 
 // own, so each has exactly one segment per window, and its flush is a plain
 // add into the workgroup's LDS stash row; the stash goes to the output with
 // one atomic per (row, rank) when the workgroup ends.
-template <int LPN, int RPL, typename FT, int N, bool BIG>
+template <int LPN, int RPL, typename FT, int N, bool BIG, bool STASH>
 __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   constexpr int G = kWin / LPN;                 // groups of LPN lanes
   constexpr int PPG = kWin / G;                 // grouped positions per group (= LPN)
@@ -367,7 +368,8 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   __shared__ uint32_t s_hist[kBuckets];
   __shared__ uint32_t s_wsum[kWin / 64];
   extern __shared__ __align__(16) unsigned char s_dyn_win[];
-  const int K = p.nhot;                                   // frequent rows in the stash
+  // frequent rows in the stash; without STASH one window per workgroup
+  const int K = STASH ? p.nhot : 0;
   const int R = p.R;
   float* s_stash = reinterpret_cast<float*>(s_dyn_win);   // K x R
   uint32_t* s_hkey = reinterpret_cast<uint32_t*>(s_stash + (size_t)K * R);
@@ -391,6 +393,8 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
       }
     }
   }
+  // windows of this workgroup: blockIdx.x, blockIdx.x + gridDim.x, ...
+  const int64_t wstep = gridDim.x;
   // the first window's non-zero of this thread
   uint64_t nkey = 0;
   float nx = 0.f;
@@ -417,7 +421,7 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   const int p0 = g * PPG;
   const uint64_t gmask = PPG >= 64 ? ~0ULL : ((1ULL << PPG) - 1);
 
-  for (int64_t win = blockIdx.x; win < nwin; win += gridDim.x) {
+  for (int64_t win = blockIdx.x; win < nwin; win += wstep) {
     const int64_t k0 = win * kWin;
     const int nvalid = (int)min((int64_t)kWin, p.n - k0);
     const bool valid = tid < nvalid;
@@ -473,9 +477,9 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
       if (lane == 0) s_end[tid >> 6] = em;
     }
     // the next window's non-zero, in flight during this walk
-    {
-      const int64_t k = (win + gridDim.x) * kWin + tid;
-      if (win + gridDim.x < nwin && k < p.n) {
+    if constexpr (STASH) {
+      const int64_t k = (win + wstep) * kWin + tid;
+      if (win + wstep < nwin && k < p.n) {
         nkey = p.keys[k];
         nx = p.vals[k];
       }
@@ -581,6 +585,7 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
       }
       __syncthreads();
     }
+    if constexpr (!STASH) break;
   }
   // ---- the stash of frequent rows: one atomic per (row, rank) that received a term
   if (K > 0) {
@@ -1162,18 +1167,23 @@ static KernelFn pick_tile(int N) {
   }
 }
 
-template <int LPN, int RPL, typename FT, bool BIG>
-static KernelFn pick_win(int N) {
+template <int LPN, int RPL, typename FT, bool BIG, bool STASH>
+static KernelFn pick_win_s(int N) {
   switch (N) {
-    case 1: return k_mttkrp_win<LPN, RPL, FT, 1, BIG>;
-    case 2: return k_mttkrp_win<LPN, RPL, FT, 2, BIG>;
-    case 3: return k_mttkrp_win<LPN, RPL, FT, 3, BIG>;
-    case 4: return k_mttkrp_win<LPN, RPL, FT, 4, BIG>;
-    case 5: return k_mttkrp_win<LPN, RPL, FT, 5, BIG>;
-    case 6: return k_mttkrp_win<LPN, RPL, FT, 6, BIG>;
-    case 7: return k_mttkrp_win<LPN, RPL, FT, 7, BIG>;
-    default: return k_mttkrp_win<LPN, RPL, FT, 8, BIG>;
+    case 1: return k_mttkrp_win<LPN, RPL, FT, 1, BIG, STASH>;
+    case 2: return k_mttkrp_win<LPN, RPL, FT, 2, BIG, STASH>;
+    case 3: return k_mttkrp_win<LPN, RPL, FT, 3, BIG, STASH>;
+    case 4: return k_mttkrp_win<LPN, RPL, FT, 4, BIG, STASH>;
+    case 5: return k_mttkrp_win<LPN, RPL, FT, 5, BIG, STASH>;
+    case 6: return k_mttkrp_win<LPN, RPL, FT, 6, BIG, STASH>;
+    case 7: return k_mttkrp_win<LPN, RPL, FT, 7, BIG, STASH>;
+    default: return k_mttkrp_win<LPN, RPL, FT, 8, BIG, STASH>;
   }
+}
+
+template <int LPN, int RPL, typename FT, bool BIG>
+static KernelFn pick_win(int N, bool stash) {
+  return stash ? pick_win_s<LPN, RPL, FT, BIG, true>(N) : pick_win_s<LPN, RPL, FT, BIG, false>(N);
 }
 
 typedef void (*StashFn)(KParams, StashCfg);
@@ -1302,16 +1312,17 @@ static KernelFn select_tile(int N, int R, int fdt) {
 // the Zipf workloads: R <= 16: 16 x 1; R <= 32: 16 x 2 (8 x 4 was 1.8x slower);
 // R <= 64: 16 x 4 (10% faster than 32 x 2); larger: 64 x 2 per pass over the rank
 template <typename FT, bool BIG>
-static KernelFn select_win_t(int N, int R) {
-  if (R <= 16) return pick_win<16, 1, FT, BIG>(N);
-  if (R <= 32) return pick_win<16, 2, FT, BIG>(N);
-  if (R <= 64) return pick_win<16, 4, FT, BIG>(N);
-  return pick_win<64, 2, FT, BIG>(N);
+static KernelFn select_win_t(int N, int R, bool stash) {
+  if (R <= 16) return pick_win<16, 1, FT, BIG>(N, stash);
+  if (R <= 32) return pick_win<16, 2, FT, BIG>(N, stash);
+  if (R <= 64) return pick_win<16, 4, FT, BIG>(N, stash);
+  return pick_win<64, 2, FT, BIG>(N, stash);
 }
 
-static KernelFn select_win(int N, int R, int fdt, bool big) {
-  if (fdt == BLCO_F32) return big ? select_win_t<float, true>(N, R) : select_win_t<float, false>(N, R);
-  return big ? select_win_t<uint16_t, true>(N, R) : select_win_t<uint16_t, false>(N, R);
+static KernelFn select_win(int N, int R, int fdt, bool big, bool stash) {
+  if (fdt == BLCO_F32)
+    return big ? select_win_t<float, true>(N, R, stash) : select_win_t<float, false>(N, R, stash);
+  return big ? select_win_t<uint16_t, true>(N, R, stash) : select_win_t<uint16_t, false>(N, R, stash);
 }
 
 static KernelFn select_loss(int N, int R, int fdt) {
@@ -1547,7 +1558,7 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
     if (lds > 65536) HIPCHK(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(f, dim3((unsigned)nwg), dim3(kSB), lds, s, p, cfg);
   } else if (var == kVarWin) {
-    KernelFn f = select_win(t->lay.N, rank, fdt, big);
+    KernelFn f = select_win(t->lay.N, rank, fdt, big, true);
     const int64_t nwin = (n + kWin - 1) / kWin;
     // frequent rows of the target mode kept in the LDS stash: as many as fit
     // beside the kernel's own LDS in one workgroup's share of a CU
@@ -1557,12 +1568,25 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
       const size_t budget = win_lds_budget();
       if (budget > fixed)
         K = (int)std::min<size_t>((size_t)t->nhot[mode], (budget - fixed) / ((size_t)rank * 4));
+      // a stash shortens the longest atomic chains only if the rows left out
+      // are much less frequent than the most frequent one (measured slower on
+      // a 1024-row uniform mode, where a fifth of the rows fit); an explicit
+      // threshold at build time keeps the stash regardless
+      if (K > 0 && !t->hot_forced) {
+        const uint64_t* cnt = t->hot_cnt.data() + (size_t)mode * (kHotMax + 1);
+        if (cnt[K] * 4 > cnt[0]) K = 0;
+      }
     }
     p.hot = t->d_hot + (size_t)mode * kHotMax;
     p.nhot = K;
+    if (K == 0) f = select_win(t->lay.N, rank, fdt, big, false);
     const size_t dyn = K > 0 ? (size_t)K * rank * 4 + 2 * (size_t)kHotSlots * 4 : 0;
-    // persistent: two resident workgroups per CU take the windows in turn
-    const int64_t grid = std::min<int64_t>(nwin, (int64_t)device_cus() * 2);
+    // with a stash: persistent workgroups, kWinRounds times the resident count
+    // (two per CU), which balances the end of the launch (measured 1-2% faster
+    // than one round) at the cost of more stash flushes; without one: a
+    // workgroup per window (measured about 1% faster than persistent ones)
+    const int64_t grid =
+        K > 0 ? std::min<int64_t>(nwin, (int64_t)device_cus() * 2 * kWinRounds) : nwin;
     hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kWin), dyn, s, p);
   } else {
     int64_t tiles = (n + 63) / 64;
@@ -1645,6 +1669,7 @@ extern "C" int blco_build(int nmodes, const uint64_t* dims, int64_t nnz,
     placement = opts->placement;
     if (opts->hot_min_count != 0) hot_min = opts->hot_min_count;
   }
+  const bool hot_forced = opts && opts->hot_min_count > 0;
   if (placement != BLCO_PLACE_DEVICE && placement != BLCO_PLACE_PINNED &&
       placement != BLCO_PLACE_HOST)
     return set_error(BLCO_EINVAL, "placement %d", placement);
@@ -1663,6 +1688,7 @@ extern "C" int blco_build(int nmodes, const uint64_t* dims, int64_t nnz,
     return rc;
   }
   find_hot_rows(coords, nnz, hot_min, t);
+  t->hot_forced = hot_forced;
   if (placement == BLCO_PLACE_HOST) {
     *out = t;
     return BLCO_OK;

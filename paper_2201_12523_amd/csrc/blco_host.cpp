@@ -347,6 +347,7 @@ int host_build(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_t* co
 void find_hot_rows(const uint32_t* const* coords, int64_t nnz, int64_t min_count, blco_tensor* t) {
   const int N = t->lay.N;
   t->hot.assign((size_t)N * kHotMax, 0xFFFFFFFFu);
+  t->hot_cnt.assign((size_t)N * (kHotMax + 1), 0);
   for (int n = 0; n < N; ++n) t->nhot[n] = 0;
   if (nnz <= 0 || min_count < 0) return;
   const int64_t step = std::max<int64_t>(1, nnz / ((int64_t)1 << 22));
@@ -357,19 +358,24 @@ void find_hot_rows(const uint32_t* const* coords, int64_t nnz, int64_t min_count
       const uint64_t I = t->lay.dims[n];
       std::vector<uint32_t> cnt((size_t)I, 0);
       for (int64_t i = 0; i < nnz; i += step) ++cnt[coords[n][i]];
-      // candidates above the sampled threshold, most frequent first
+      // the kHotMax + 1 most frequent rows; those reaching the sampled
+      // threshold are the frequent rows, and all their counts are kept
       const uint64_t need = (uint64_t)std::max<int64_t>(1, (min_count + step - 1) / step);
       std::vector<std::pair<uint32_t, uint32_t>> c;
       for (uint64_t r = 0; r < I; ++r)
-        if (cnt[r] >= need) c.push_back({cnt[r], (uint32_t)r});
-      const size_t k = std::min<size_t>(c.size(), kHotMax);
+        if (cnt[r] > 0) c.push_back({cnt[r], (uint32_t)r});
+      const size_t k = std::min<size_t>(c.size(), kHotMax + 1);
       std::partial_sort(c.begin(), c.begin() + k, c.end(),
                         [](const std::pair<uint32_t, uint32_t>& a,
                            const std::pair<uint32_t, uint32_t>& b) {
                           return a.first != b.first ? a.first > b.first : a.second < b.second;
                         });
-      for (size_t j = 0; j < k; ++j) t->hot[(size_t)n * kHotMax + j] = c[j].second;
-      t->nhot[n] = (int)k;
+      int nh = 0;
+      for (size_t j = 0; j < k; ++j) {
+        t->hot_cnt[(size_t)n * (kHotMax + 1) + j] = (uint64_t)c[j].first * (uint64_t)step;
+        if (j < (size_t)kHotMax && c[j].first >= need) t->hot[(size_t)n * kHotMax + nh++] = c[j].second;
+      }
+      t->nhot[n] = nh;
     });
   }
   for (auto& x : th) x.join();

@@ -74,7 +74,9 @@ struct blco_tensor {
   // frequent rows of each mode (kHotMax per mode, most frequent first, padded
   // with 0xFFFFFFFF): the register-based kernel sums them per workgroup in LDS
   std::vector<uint32_t> hot;         // N * kHotMax
+  std::vector<uint64_t> hot_cnt;     // N * (kHotMax + 1): estimated counts of the most frequent rows
   int nhot[BLCO_MAX_MODES] = {};
+  bool hot_forced = false;           // an explicit threshold: stash whatever fits
   uint32_t* d_hot = nullptr;
 };
 
