@@ -126,6 +126,21 @@ int blco_build(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_t* co
                const float* values, const blco_build_opts* opts, blco_tensor** out);
 
 /*
+ * blco_build on the GPU: coords is a host array of nmodes DEVICE pointers
+ * (nnz 0-based indices each), values a DEVICE array of nnz; both stay owned by
+ * the caller and may be freed on return.  Linearization, a stable radix sort
+ * along the encoding line, re-encoding, run detection and the frequent-row
+ * counts run on `stream`; the block list and per-run tables are finished on
+ * the host.  The result equals blco_build's for the same input, bit for bit.
+ * Placement DEVICE or PINNED (the non-zeros are copied to pinned memory).
+ * nnz < 2^31 - 1.  Synchronous.  Errors: as blco_build, EUNSUPPORTED for
+ * larger nnz, EINVAL for placement HOST.
+ */
+int blco_build_device(int nmodes, const uint64_t* dims, int64_t nnz,
+                      const uint32_t* const* coords, const float* values,
+                      const blco_build_opts* opts, void* stream, blco_tensor** out);
+
+/*
  * Mode-`mode` MTTKRP (Eq. (1); Figure 3; Sections 5.1-5.2) of an in-memory
  * tensor (placement DEVICE):
  *   out[i, r] = sum over non-zeros k with i_mode = i of x_k * prod_{m != mode} A^(m)[i_m, r]

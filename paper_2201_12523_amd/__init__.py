@@ -33,7 +33,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: 
 EXPORTED = ["blco_build", "blco_mttkrp", "blco_mttkrp_acc", "blco_mttkrp_v", "blco_mttkrp_stream",
             "blco_mttkrp_stream_all",
             "blco_sampled_loss", "blco_cast_bf16", "blco_set_resolution", "blco_resolution",
-            "blco_gram", "blco_cp_als",
+            "blco_gram", "blco_cp_als", "blco_build_device",
             "blco_info", "blco_export", "blco_free",
             "blco_last_error"]
 
@@ -95,6 +95,8 @@ def lib():
         L.blco_info.argtypes = [p, ctypes.POINTER(_Info)]
         L.blco_export.argtypes = [p, p, p, p, p]
         L.blco_set_resolution.argtypes = [p, i32]
+        L.blco_build_device.argtypes = [i32, p, i64, p, p, ctypes.POINTER(_Opts), p,
+                                        ctypes.POINTER(p)]
         L.blco_gram.argtypes = [p, i32, i64, i32, p, p]
         L.blco_cp_als.argtypes = [p, p, i32, ctypes.POINTER(_CPALSOpts), p,
                                   ctypes.POINTER(_CPALSReport), p]
@@ -210,6 +212,42 @@ def build(coords, values, dims, key_bits=64, max_block_nnz=1 << 27, placement="d
     h = ctypes.c_void_p()
     _check(lib().blco_build(N, d.ctypes.data, len(v), arr, v.ctypes.data, ctypes.byref(opts),
                             ctypes.byref(h)))
+    return BLCOTensor(h.value, dims)
+
+
+def build_device(coords, values, dims, key_bits=64, max_block_nnz=1 << 27, placement="device",
+                 hot_min_count=0, stream=None):
+    """blco_build on the GPU.  coords: N index arrays (numpy, or int32 device tensors holding
+    the uint32 bits); values: float32 (numpy or device tensor).  Same result as build()."""
+    N = len(dims)
+    if len(coords) != N:
+        raise ValueError("one coordinate array per mode")
+    dev = torch.device("cuda", torch.cuda.current_device())
+    keep = []
+    for c in coords:
+        if isinstance(c, torch.Tensor):
+            if not c.is_cuda or c.dtype != torch.int32 or not c.is_contiguous():
+                raise ValueError("device coordinates must be contiguous int32 tensors")
+            keep.append(c)
+        else:
+            a = np.ascontiguousarray(c, dtype=np.uint32).view(np.int32)
+            keep.append(torch.from_numpy(a).to(dev))
+    if isinstance(values, torch.Tensor):
+        if not values.is_cuda or values.dtype != torch.float32 or not values.is_contiguous():
+            raise ValueError("device values must be a contiguous float32 tensor")
+        v = values
+    else:
+        v = torch.from_numpy(np.ascontiguousarray(values, dtype=np.float32)).to(dev)
+    nnz = v.numel()
+    for c in keep:
+        if c.numel() != nnz:
+            raise ValueError("coordinate arrays and values differ in length")
+    d = np.ascontiguousarray(dims, dtype=np.uint64)
+    arr = (ctypes.c_void_p * N)(*[c.data_ptr() for c in keep])
+    opts = _Opts(key_bits, max_block_nnz, PLACEMENTS[placement], int(hot_min_count))
+    h = ctypes.c_void_p()
+    _check(lib().blco_build_device(N, d.ctypes.data, nnz, arr, v.data_ptr(), ctypes.byref(opts),
+                                   _stream(stream), ctypes.byref(h)))
     return BLCOTensor(h.value, dims)
 
 

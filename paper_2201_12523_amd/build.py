@@ -1,8 +1,8 @@
 """Compile the BLCO library for gfx950 into ``paper_2201_12523_amd/libblco.so``.
 
 Host builder (``csrc/blco_host.cpp``) with g++; device runtime and MTTKRP
-kernels (``csrc/blco_device.hip``) and the CP-ALS driver (``csrc/blco_cpals.hip``)
-with hipcc; linked with hipcc.  Run as
+kernels (``csrc/blco_device.hip``), the CP-ALS driver (``csrc/blco_cpals.hip``) and
+the GPU builder (``csrc/blco_build_gpu.hip``) with hipcc; linked with hipcc.  Run as
 ``python -m paper_2201_12523_amd.build``.
 """
 from __future__ import annotations
@@ -38,6 +38,7 @@ def build(verbose: bool = True) -> str:
     host_o = os.path.join(BUILD_DIR, "blco_host.o")
     dev_o = os.path.join(BUILD_DIR, "blco_device.o")
     als_o = os.path.join(BUILD_DIR, "blco_cpals.o")
+    gb_o = os.path.join(BUILD_DIR, "blco_build_gpu.o")
     t = time.time()
     # the three objects compile in parallel
     procs = [subprocess.Popen(["g++", "-std=c++17", "-O3", "-fPIC", "-Wall", "-c",
@@ -45,14 +46,16 @@ def build(verbose: bool = True) -> str:
              subprocess.Popen([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "blco_device.hip"),
                                "-o", dev_o]),
              subprocess.Popen([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "blco_cpals.hip"),
-                               "-o", als_o])]
+                               "-o", als_o]),
+             subprocess.Popen([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "blco_build_gpu.hip"),
+                               "-o", gb_o])]
     codes = [p.wait() for p in procs]
     if any(codes):
         raise subprocess.CalledProcessError(max(codes, key=abs), "compile")
     t1 = t2 = time.time() - t
     tmp = OUT + ".tmp"
-    t3 = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, dev_o, als_o, "-o",
-               tmp, "-lpthread"])
+    t3 = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, dev_o, als_o, gb_o,
+               "-o", tmp, "-lpthread"])
     os.replace(tmp, OUT)
     if verbose:
         print(f"built {OUT} (compile {t1:.1f}s, link {t3:.1f}s)", file=sys.stderr)

@@ -1,0 +1,446 @@
+// BLCO construction on the GPU (Sections 4.1-4.2), from coordinates and values
+// already in device memory.
+//
+// Steps, each a kernel or a device-wide primitive on the caller's stream:
+//   1. ALTO linearization of every coordinate (Section 4.1): bit j of mode n
+//      goes to position pos[n][j] of a 64- or 128-bit index; out-of-range
+//      coordinates are flagged;
+//   2. a stable radix sort of (index, non-zero number) pairs: one pass over the
+//      low 64 bits, then, for indices over 64 bits, one over the high bits of
+//      the indices gathered in that order (least significant digits first);
+//   3. re-encoding in sorted order (Figure 6b): the key holds the low w_n bits
+//      of each mode at shift s_n; the block key is the index above bit K;
+//   4. runs of equal block key (flags and a select), copied to the host, where
+//      the block list, per-run high bits and tile table are finished by the
+//      same code as the host builder;
+//   5. the frequent rows of each mode (sampled counts, a descending radix sort).
+// The result equals blco_build's bit for bit.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "blco_internal.h"
+
+using namespace blco;
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return set_error(BLCO_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+namespace {
+
+struct LinParams {
+  const uint32_t* coords[BLCO_MAX_MODES];
+  uint64_t dims[BLCO_MAX_MODES];
+  uint8_t pos[BLCO_MAX_MODES][32];
+  int b[BLCO_MAX_MODES];
+  int w[BLCO_MAX_MODES];
+  int s[BLCO_MAX_MODES];
+  int N;
+  int K;
+  int T;
+};
+
+// ALTO index of every non-zero (lo: bits 0..63, hi: bits 64..127) and its
+// number; *bad = smallest non-zero number with a coordinate out of range.
+__global__ __launch_bounds__(256) void k_linearize(LinParams p, int64_t n, uint64_t* __restrict__ lo,
+                                                   uint64_t* __restrict__ hi,
+                                                   uint32_t* __restrict__ idx,
+                                                   unsigned long long* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  uint64_t l = 0, h = 0;
+  for (int m = 0; m < p.N; ++m) {
+    uint32_t c = p.coords[m][i];
+    if ((uint64_t)c >= p.dims[m]) {
+      atomicMin(bad, (unsigned long long)i);
+      c = 0;
+    }
+    for (int j = 0; j < p.b[m]; ++j) {
+      const uint64_t bit = (c >> j) & 1u;
+      const int q = p.pos[m][j];
+      if (q < 64)
+        l |= bit << q;
+      else
+        h |= bit << (q - 64);
+    }
+  }
+  lo[i] = l;
+  if (hi) hi[i] = h;
+  idx[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_gather_u64(const uint64_t* __restrict__ src,
+                                                    const uint32_t* __restrict__ idx, int64_t n,
+                                                    uint64_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+// Keys, values and block keys in sorted order; start flags of runs.
+__global__ __launch_bounds__(256) void k_encode(LinParams p, int64_t n,
+                                                const uint32_t* __restrict__ perm,
+                                                const uint64_t* __restrict__ lo,
+                                                const uint64_t* __restrict__ hi,
+                                                const float* __restrict__ vals,
+                                                uint64_t* __restrict__ keys,
+                                                float* __restrict__ vout,
+                                                uint64_t* __restrict__ bkey) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t src = perm[i];
+  uint64_t key = 0;
+  for (int m = 0; m < p.N; ++m) {
+    const uint64_t c = p.coords[m][src];
+    const uint64_t mask = p.w[m] >= 64 ? ~0ULL : ((1ULL << p.w[m]) - 1);
+    key |= (c & mask) << p.s[m];
+  }
+  keys[i] = key;
+  vout[i] = vals[src];
+  // block key: the index above bit K
+  const uint64_t l = lo[src], h = hi ? hi[src] : 0;
+  uint64_t B;
+  if (p.K >= 128)
+    B = 0;
+  else if (p.K >= 64)
+    B = h >> (p.K - 64);
+  else if (p.K == 0)
+    B = l;
+  else
+    B = (l >> p.K) | (h << (64 - p.K));
+  bkey[i] = B;
+}
+
+__global__ __launch_bounds__(256) void k_run_flags(const uint64_t* __restrict__ bkey, int64_t n,
+                                                   uint8_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) flag[i] = (i == 0 || bkey[i] != bkey[i - 1]) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_gather_keys(const uint64_t* __restrict__ bkey,
+                                                     const int64_t* __restrict__ starts,
+                                                     int64_t nruns, uint64_t* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r < nruns) out[r] = bkey[starts[r]];
+}
+
+__global__ __launch_bounds__(256) void k_count_sampled(const uint32_t* __restrict__ c, int64_t n,
+                                                       int64_t step, uint32_t* __restrict__ cnt) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = s * step;
+  if (i < n) atomicAdd(&cnt[c[i]], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_iota_u32(uint32_t* __restrict__ a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) a[i] = (uint32_t)i;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v) { *p = v; }
+
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* __restrict__ a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+unsigned grid_of(int64_t n) { return (unsigned)std::max<int64_t>((n + 255) / 256, 1); }
+
+// device allocations released on every return path
+struct Pool {
+  std::vector<void*> ptrs;
+  ~Pool() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  int get(T** out, size_t count) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
+      return set_error(BLCO_ENOMEM, "device allocation of %zu bytes failed",
+                       std::max<size_t>(count, 1) * sizeof(T));
+    ptrs.push_back(p);
+    *out = static_cast<T*>(p);
+    return BLCO_OK;
+  }
+};
+
+template <typename T>
+int upload_to(T** dst, const T* src, size_t count, hipStream_t s, size_t* acc) {
+  const size_t bytes = sizeof(T) * std::max<size_t>(count, 1);
+  HIPCHK(hipMalloc((void**)dst, bytes));
+  if (count) HIPCHK(hipMemcpyAsync(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice, s));
+  *acc += bytes;
+  return BLCO_OK;
+}
+
+void release_tensor_arrays(blco_tensor* t) {
+  for (void* p : {(void*)t->d_keys, (void*)t->d_vals, (void*)t->d_run_start,
+                  (void*)t->d_run_base, (void*)t->d_tile_run, (void*)t->d_hot})
+    if (p) (void)hipFree(p);
+  t->d_keys = nullptr;
+  t->d_vals = nullptr;
+  t->d_run_start = nullptr;
+  t->d_run_base = nullptr;
+  t->d_tile_run = nullptr;
+  t->d_hot = nullptr;
+  free_host_arrays(t);
+}
+
+void pinned_release(void* p) { (void)hipHostFree(p); }
+
+// Frequent rows of every mode, as find_hot_rows: counts over every step-th
+// non-zero, the kHotMax + 1 most frequent rows (ties by row), the frequent
+// ones reaching the threshold.
+int gpu_hot_rows(const LinParams& lp, int64_t nnz, int64_t min_count, Pool& pool, hipStream_t s,
+                 blco_tensor* t) {
+  const int N = lp.N;
+  t->hot.assign((size_t)N * kHotMax, 0xFFFFFFFFu);
+  t->hot_cnt.assign((size_t)N * (kHotMax + 1), 0);
+  for (int n = 0; n < N; ++n) t->nhot[n] = 0;
+  if (nnz <= 0 || min_count < 0) return BLCO_OK;
+  const int64_t step = std::max<int64_t>(1, nnz / ((int64_t)1 << 22));
+  const int64_t samples = (nnz + step - 1) / step;
+  const uint64_t need = (uint64_t)std::max<int64_t>(1, (min_count + step - 1) / step);
+  int rc;
+  for (int n = 0; n < N; ++n) {
+    const uint64_t I = lp.dims[n];
+    if (I > ((uint64_t)1 << 26)) continue;
+    uint32_t *cnt, *cnt2, *row, *row2;
+    if ((rc = pool.get(&cnt, I)) || (rc = pool.get(&cnt2, I)) || (rc = pool.get(&row, I)) ||
+        (rc = pool.get(&row2, I)))
+      return rc;
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_of((int64_t)I)), dim3(256), 0, s, cnt, (int64_t)I);
+    hipLaunchKernelGGL(k_count_sampled, dim3(grid_of(samples)), dim3(256), 0, s, lp.coords[n],
+                       nnz, step, cnt);
+    hipLaunchKernelGGL(k_iota_u32, dim3(grid_of((int64_t)I)), dim3(256), 0, s, row, (int64_t)I);
+    HIPCHK(hipGetLastError());
+    size_t tmp_bytes = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp_bytes, cnt, cnt2, row, row2,
+                                                        (int)I, 0, 32, s));
+    void* tmp;
+    if ((rc = pool.get((char**)&tmp, tmp_bytes))) return rc;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tmp_bytes, cnt, cnt2, row, row2,
+                                                        (int)I, 0, 32, s));
+    const size_t k = std::min<size_t>((size_t)I, kHotMax + 1);
+    std::vector<uint32_t> hc(k), hr(k);
+    HIPCHK(hipMemcpyAsync(hc.data(), cnt2, k * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hr.data(), row2, k * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int nh = 0;
+    for (size_t j = 0; j < k && hc[j] > 0; ++j) {
+      t->hot_cnt[(size_t)n * (kHotMax + 1) + j] = (uint64_t)hc[j] * (uint64_t)step;
+      if (j < (size_t)kHotMax && hc[j] >= need) t->hot[(size_t)n * kHotMax + nh++] = hr[j];
+    }
+    t->nhot[n] = nh;
+  }
+  return BLCO_OK;
+}
+
+int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_t* const* coords,
+                    const float* values, int key_bits, int64_t cap, int64_t hot_min,
+                    hipStream_t s, blco_tensor* t) {
+  int rc = make_layout(nmodes, dims, key_bits, &t->lay);
+  if (rc) return rc;
+  const Layout& L = t->lay;
+  t->nnz = nnz;
+  t->max_block_nnz = cap;
+  LinParams lp;
+  memset(&lp, 0, sizeof(lp));
+  lp.N = L.N;
+  lp.K = L.K;
+  lp.T = L.T;
+  for (int m = 0; m < L.N; ++m) {
+    lp.coords[m] = coords[m];
+    lp.dims[m] = L.dims[m];
+    lp.b[m] = L.b[m];
+    lp.w[m] = L.w[m];
+    lp.s[m] = L.s[m];
+    for (int j = 0; j < L.b[m]; ++j) lp.pos[m][j] = (uint8_t)L.pos[m][j];
+  }
+  Pool pool;
+  const bool wide = L.T > 64;
+  uint64_t *lo, *lo2, *hi = nullptr, *hi2 = nullptr, *bkey;
+  uint32_t *idx, *perm, *perm2;
+  unsigned long long* bad;
+  if ((rc = pool.get(&lo, nnz)) || (rc = pool.get(&lo2, nnz)) || (rc = pool.get(&idx, nnz)) ||
+      (rc = pool.get(&perm, nnz)) || (rc = pool.get(&bkey, nnz)) || (rc = pool.get(&bad, 1)))
+    return rc;
+  if (wide && ((rc = pool.get(&hi, nnz)) || (rc = pool.get(&hi2, nnz)) || (rc = pool.get(&perm2, nnz))))
+    return rc;
+  // 1. linearize
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s, bad, ~0ULL);
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_linearize, dim3(grid_of(nnz)), dim3(256), 0, s, lp, nnz, lo, hi, idx, bad);
+  HIPCHK(hipGetLastError());
+  unsigned long long first_bad = ~0ULL;
+  HIPCHK(hipMemcpyAsync(&first_bad, bad, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (first_bad != ~0ULL) {
+    const int64_t i = (int64_t)first_bad;
+    for (int m = 0; m < L.N; ++m) {
+      uint32_t c = 0;
+      HIPCHK(hipMemcpy(&c, coords[m] + i, 4, hipMemcpyDeviceToHost));
+      if ((uint64_t)c >= L.dims[m])
+        return set_error(BLCO_ERANGE, "coordinate %u of mode %d at non-zero %lld is >= %llu", c, m,
+                         (long long)i, (unsigned long long)L.dims[m]);
+    }
+    return set_error(BLCO_ERANGE, "coordinate out of range at non-zero %lld", (long long)i);
+  }
+  // 2. stable sort along the encoding line
+  if (nnz > 0) {
+    const int nb0 = std::max(1, std::min(L.T, 64));
+    size_t tmp_bytes = 0, t2 = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, lo, lo2, idx, perm, (int)nnz, 0,
+                                              nb0, s));
+    if (wide)
+      HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, t2, hi2, hi, perm, perm2, (int)nnz, 0,
+                                                L.T - 64, s));
+    void* tmp;
+    if ((rc = pool.get((char**)&tmp, std::max(tmp_bytes, t2)))) return rc;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, lo, lo2, idx, perm, (int)nnz, 0, nb0,
+                                              s));
+    if (wide) {
+      // the high bits in that order, then a stable pass over them (the
+      // original lo and hi stay in place for the re-encoding)
+      hipLaunchKernelGGL(k_gather_u64, dim3(grid_of(nnz)), dim3(256), 0, s, hi, perm, nnz, hi2);
+      HIPCHK(hipGetLastError());
+      uint64_t* hi_sorted;
+      if ((rc = pool.get(&hi_sorted, nnz))) return rc;
+      HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp, t2, hi2, hi_sorted, perm, perm2, (int)nnz, 0,
+                                                L.T - 64, s));
+      std::swap(perm, perm2);
+    }
+  }
+  // 3. re-encode in sorted order; keys and values go straight into the tensor
+  size_t acc = 0;
+  HIPCHK(hipMalloc((void**)&t->d_keys, sizeof(uint64_t) * std::max<int64_t>(nnz, 1)));
+  HIPCHK(hipMalloc((void**)&t->d_vals, sizeof(float) * std::max<int64_t>(nnz, 1)));
+  acc += (sizeof(uint64_t) + sizeof(float)) * (size_t)std::max<int64_t>(nnz, 1);
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_encode, dim3(grid_of(nnz)), dim3(256), 0, s, lp, nnz, perm, lo, hi, values,
+                       t->d_keys, t->d_vals, bkey);
+    HIPCHK(hipGetLastError());
+  }
+  // 4. runs of equal block key
+  std::vector<int64_t> run_start;
+  std::vector<uint64_t> run_key;
+  if (nnz > 0) {
+    uint8_t* flag;
+    int64_t* starts;
+    int64_t* nsel;
+    uint64_t* keys_at;
+    if ((rc = pool.get(&flag, nnz)) || (rc = pool.get(&starts, nnz)) || (rc = pool.get(&nsel, 1)))
+      return rc;
+    hipLaunchKernelGGL(k_run_flags, dim3(grid_of(nnz)), dim3(256), 0, s, bkey, nnz, flag);
+    HIPCHK(hipGetLastError());
+    hipcub::CountingInputIterator<int64_t> it(0);
+    size_t tmp_bytes = 0;
+    HIPCHK(hipcub::DeviceSelect::Flagged(nullptr, tmp_bytes, it, flag, starts, nsel, (int)nnz, s));
+    void* tmp;
+    if ((rc = pool.get((char**)&tmp, tmp_bytes))) return rc;
+    HIPCHK(hipcub::DeviceSelect::Flagged(tmp, tmp_bytes, it, flag, starts, nsel, (int)nnz, s));
+    int64_t nruns = 0;
+    HIPCHK(hipMemcpyAsync(&nruns, nsel, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if ((rc = pool.get(&keys_at, nruns))) return rc;
+    hipLaunchKernelGGL(k_gather_keys, dim3(grid_of(nruns)), dim3(256), 0, s, bkey, starts, nruns,
+                       keys_at);
+    HIPCHK(hipGetLastError());
+    run_start.resize((size_t)nruns);
+    run_key.resize((size_t)nruns);
+    HIPCHK(hipMemcpyAsync(run_start.data(), starts, 8 * nruns, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(run_key.data(), keys_at, 8 * nruns, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  finish_runs(L, nnz, run_start, run_key, cap, t);
+  // 5. frequent rows
+  if ((rc = gpu_hot_rows(lp, nnz, hot_min, pool, s, t))) return rc;
+  if ((rc = upload_to(&t->d_run_start, t->run_start.data(), t->run_start.size(), s, &acc)) ||
+      (rc = upload_to(&t->d_run_base, t->run_base.data(), t->run_base.size(), s, &acc)) ||
+      (rc = upload_to(&t->d_tile_run, t->tile_run.data(), t->tile_run.size(), s, &acc)) ||
+      (rc = upload_to(&t->d_hot, t->hot.data(), t->hot.size(), s, &acc)))
+    return rc;
+  HIPCHK(hipStreamSynchronize(s));
+  t->device_bytes = acc;
+  return BLCO_OK;
+}
+
+}  // namespace
+
+extern "C" int blco_build_device(int nmodes, const uint64_t* dims, int64_t nnz,
+                                 const uint32_t* const* coords, const float* values,
+                                 const blco_build_opts* opts, void* stream, blco_tensor** out) {
+  clear_error();
+  if (!out) return set_error(BLCO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nmodes < 1 || nmodes > BLCO_MAX_MODES)
+    return set_error(BLCO_EUNSUPPORTED, "nmodes %d outside 1..%d", nmodes, BLCO_MAX_MODES);
+  if (!dims) return set_error(BLCO_EINVAL, "dims is NULL");
+  if (nnz < 0) return set_error(BLCO_EINVAL, "nnz %lld < 0", (long long)nnz);
+  if (nnz >= ((int64_t)1 << 31) - 1)
+    return set_error(BLCO_EUNSUPPORTED, "the GPU builder takes fewer than 2^31 - 1 non-zeros");
+  if (nnz > 0 && (!coords || !values)) return set_error(BLCO_EINVAL, "coords or values is NULL");
+  for (int n = 0; n < nmodes; ++n) {
+    if (dims[n] < 1) return set_error(BLCO_EINVAL, "dims[%d] = 0", n);
+    if (dims[n] > (1ULL << 32))
+      return set_error(BLCO_EUNSUPPORTED, "dims[%d] = %llu > 2^32", n, (unsigned long long)dims[n]);
+    if (nnz > 0 && !coords[n]) return set_error(BLCO_EINVAL, "coords[%d] is NULL", n);
+  }
+  int key_bits = 64;
+  int64_t cap = (int64_t)1 << 27;
+  int placement = BLCO_PLACE_DEVICE;
+  int64_t hot_min = kHotMinCount;
+  if (opts) {
+    key_bits = opts->key_bits;
+    cap = opts->max_block_nnz;
+    placement = opts->placement;
+    if (opts->hot_min_count != 0) hot_min = opts->hot_min_count;
+  }
+  if (key_bits < 1 || key_bits > 64) return set_error(BLCO_EINVAL, "key_bits %d outside 1..64", key_bits);
+  if (cap < 1) return set_error(BLCO_EINVAL, "max_block_nnz < 1");
+  if (placement != BLCO_PLACE_DEVICE && placement != BLCO_PLACE_PINNED)
+    return set_error(BLCO_EINVAL, "the GPU builder places the tensor on the device or in pinned memory");
+  blco_tensor* t = new (std::nothrow) blco_tensor();
+  if (!t) return set_error(BLCO_ENOMEM, "host allocation failed");
+  t->placement = placement;
+  t->hot_forced = opts && opts->hot_min_count > 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&t->device) != hipSuccess) {
+    delete t;
+    return set_error(BLCO_EDEVICE, "hipGetDevice failed");
+  }
+  int rc = build_on_device(nmodes, dims, nnz, coords, values, key_bits, cap, hot_min, s, t);
+  if (rc == BLCO_OK && placement == BLCO_PLACE_PINNED) {
+    // the non-zeros move to pinned host memory for streaming
+    const size_t n1 = (size_t)std::max<int64_t>(nnz, 1);
+    if (hipHostMalloc((void**)&t->h_keys, n1 * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&t->h_vals, n1 * 4, hipHostMallocDefault) != hipSuccess) {
+      rc = set_error(BLCO_ENOMEM, "pinned allocation of %lld non-zeros failed", (long long)nnz);
+    } else {
+      t->host_free = pinned_release;
+      if (hipMemcpy(t->h_keys, t->d_keys, (size_t)nnz * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(t->h_vals, t->d_vals, (size_t)nnz * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+        rc = set_error(BLCO_EDEVICE, "copy of the non-zeros to pinned memory failed");
+      } else {
+        (void)hipFree(t->d_keys);
+        (void)hipFree(t->d_vals);
+        t->d_keys = nullptr;
+        t->d_vals = nullptr;
+        t->device_bytes -= n1 * 12;
+      }
+    }
+  }
+  if (rc != BLCO_OK) {
+    release_tensor_arrays(t);
+    delete t;
+    return rc;
+  }
+  *out = t;
+  return BLCO_OK;
+}

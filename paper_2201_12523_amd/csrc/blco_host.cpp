@@ -55,7 +55,7 @@ static void parallel_chunks(int64_t n, int nt, F f) {
 
 // ------------------------------------------------------------------ layout
 
-static int make_layout(int N, const uint64_t* dims, int key_bits, Layout* L) {
+int make_layout(int N, const uint64_t* dims, int key_bits, Layout* L) {
   L->N = N;
   L->T = 0;
   int maxb = 0;
@@ -163,6 +163,41 @@ static Rec* radix_sort(Rec* a, Rec* b, int64_t n, int T, int nt) {
   return a;
 }
 
+// Blocks (runs split to max_block_nnz), per-run high bits of every mode, and
+// the tile -> run table, from the runs of equal block key (Section 4.2).
+void finish_runs(const Layout& L, int64_t nnz, const std::vector<int64_t>& run_start,
+                 const std::vector<uint64_t>& run_key, int64_t max_block_nnz, blco_tensor* t) {
+  const int N = L.N;
+  t->run_start = run_start;
+  t->run_start.push_back(nnz);
+  t->block_id.clear();
+  t->block_start.clear();
+  const int64_t nruns = (int64_t)run_key.size();
+  for (int64_t r = 0; r < nruns; ++r)
+    for (int64_t c = t->run_start[r]; c < t->run_start[r + 1]; c += max_block_nnz) {
+      t->block_id.push_back(run_key[r]);
+      t->block_start.push_back(c);
+    }
+  t->block_start.push_back(nnz);
+  // high bits of every mode held by each run's block key, pre-shifted to their place
+  t->run_base.assign((size_t)nruns * N, 0);
+  for (int64_t r = 0; r < nruns; ++r)
+    for (int n = 0; n < N; ++n) {
+      uint64_t hi = 0;
+      for (int j = 0; j < L.h[n]; ++j) hi |= ((run_key[r] >> (L.pos[n][L.w[n] + j] - L.K)) & 1ULL) << j;
+      t->run_base[(size_t)r * N + n] = (uint32_t)(hi << L.w[n]);
+    }
+  // tile -> run of its first non-zero
+  int64_t ntiles = (nnz + kTile - 1) / kTile;
+  t->tile_run.resize((size_t)ntiles);
+  int64_t r = 0;
+  for (int64_t tl = 0; tl < ntiles; ++tl) {
+    int64_t e = tl * kTile;
+    while (t->run_start[r + 1] <= e) ++r;
+    t->tile_run[(size_t)tl] = (int32_t)r;
+  }
+}
+
 template <class Rec>
 static int build_with(const Layout& L, int64_t nnz, const uint32_t* const* coords,
                       const float* values, int64_t max_block_nnz, blco_tensor* t) {
@@ -229,45 +264,17 @@ static int build_with(const Layout& L, int64_t nnz, const uint32_t* const* coord
   Rec* spare = (s == a) ? b : a;
   free(spare);
 
-  // runs of equal block key, then blocks split to the cap
-  t->run_start.clear();
-  t->block_id.clear();
-  t->block_start.clear();
+  // runs of equal block key
+  std::vector<int64_t> run_start;
   std::vector<uint64_t> run_key;
   for (int64_t i = 0; i < nnz; ++i) {
     uint64_t B = shr(s[i], L.K);
     if (i == 0 || B != run_key.back()) {
       run_key.push_back(B);
-      t->run_start.push_back(i);
+      run_start.push_back(i);
     }
   }
-  t->run_start.push_back(nnz);
-  const int64_t nruns = (int64_t)run_key.size();
-  for (int64_t r = 0; r < nruns; ++r)
-    for (int64_t c = t->run_start[r]; c < t->run_start[r + 1]; c += max_block_nnz) {
-      t->block_id.push_back(run_key[r]);
-      t->block_start.push_back(c);
-    }
-  t->block_start.push_back(nnz);
-  // high bits of every mode held by each run's block key, pre-shifted to their place
-  t->run_base.assign((size_t)nruns * N, 0);
-  for (int64_t r = 0; r < nruns; ++r)
-    for (int n = 0; n < N; ++n) {
-      uint64_t hi = 0;
-      for (int j = 0; j < L.h[n]; ++j) hi |= ((run_key[r] >> (L.pos[n][L.w[n] + j] - L.K)) & 1ULL) << j;
-      t->run_base[(size_t)r * N + n] = (uint32_t)(hi << L.w[n]);
-    }
-  // tile -> run of its first non-zero
-  int64_t ntiles = (nnz + kTile - 1) / kTile;
-  t->tile_run.resize((size_t)ntiles);
-  {
-    int64_t r = 0;
-    for (int64_t tl = 0; tl < ntiles; ++tl) {
-      int64_t e = tl * kTile;
-      while (t->run_start[r + 1] <= e) ++r;
-      t->tile_run[(size_t)tl] = (int32_t)r;
-    }
-  }
+  finish_runs(L, nnz, run_start, run_key, max_block_nnz, t);
   // re-encode: every ALTO bit below K moves to its mode's field
   std::vector<uint64_t> enc(16 * 256, 0);
   {

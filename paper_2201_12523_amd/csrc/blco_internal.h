@@ -102,4 +102,13 @@ void find_hot_rows(const uint32_t* const* coords, int64_t nnz, int64_t min_count
 
 void free_host_arrays(blco_tensor* t);
 
+// Bit map of a tensor (Sections 4.1-4.2); EUNSUPPORTED when the block key
+// would need more than 64 bits.
+int make_layout(int N, const uint64_t* dims, int key_bits, Layout* L);
+
+// Blocks, per-run high bits and tile -> run table from the runs of equal
+// block key (run_start without the final nnz; run_key their block keys).
+void finish_runs(const Layout& L, int64_t nnz, const std::vector<int64_t>& run_start,
+                 const std::vector<uint64_t>& run_key, int64_t max_block_nnz, blco_tensor* t);
+
 }  // namespace blco
