@@ -159,6 +159,18 @@ def leg_inmemory(args, torch, blco, synth, w):
     inf = T.info()
     log(f"built BLCO in {build_s:.2f}s: T={inf['total_bits']} bits, {inf['nblocks']} block(s), "
         f"{inf['nruns']} run(s)")
+    # the same construction on the GPU, from device-resident coordinates and values
+    dc = [torch.from_numpy(c.view(np.int32)).to(dev) for c in coords]
+    dv = torch.from_numpy(vals).to(dev)
+    torch.cuda.synchronize()
+    gpu_build = []
+    for _ in range(3):
+        t0 = time.time()
+        Tg = blco.build_device(dc, dv, w.dims)
+        gpu_build.append(time.time() - t0)
+        Tg.free()
+    del dc, dv
+    log(f"built BLCO on the GPU in {min(gpu_build) * 1e3:.1f} ms (host builder {build_s * 1e3:.0f} ms)")
     N = len(w.dims)
     modes = list(range(N))
     distinct = [int(np.count_nonzero(np.bincount(c, minlength=d))) for c, d in zip(coords, w.dims)]
@@ -222,6 +234,7 @@ def leg_inmemory(args, torch, blco, synth, w):
     res["per_config"] = results
     res["distinct_indices"] = distinct
     res["build_s"] = build_s
+    res["build_gpu_s"] = min(gpu_build)
     res["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         import oracle
