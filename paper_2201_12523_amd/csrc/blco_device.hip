@@ -364,8 +364,11 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   constexpr int NP = NF <= 4 ? 4 : ((NF + 1) / 2) * 2;
   __shared__ __align__(16) uint32_t s_rec[kWin * NP];  // records by grouped position
   __shared__ uint64_t s_end[kWin / 64];
-  __shared__ float s_head[kWin * RPL];
-  __shared__ uint32_t s_hist[kBuckets];
+  // the histogram (processing) and the carry partial sums (computing) are never
+  // live at once: they share one array
+  constexpr int NHH = kBuckets > kWin * RPL ? kBuckets : kWin * RPL;
+  __shared__ __align__(16) uint32_t s_hist[NHH];
+  float* s_head = reinterpret_cast<float*>(s_hist);
   __shared__ uint32_t s_wsum[kWin / 64];
   extern __shared__ __align__(16) unsigned char s_dyn_win[];
   // frequent rows in the stash; without STASH one window per workgroup
