@@ -8,12 +8,14 @@
 //   2. a stable radix sort of (index, non-zero number) pairs: one pass over the
 //      low 64 bits, then, for indices over 64 bits, one over the high bits of
 //      the indices gathered in that order (least significant digits first);
-//   3. re-encoding in sorted order (Figure 6b): the key holds the low w_n bits
-//      of each mode at shift s_n; the block key is the index above bit K;
+//   3. re-encoding in sorted order (Figure 6b) from the sorted index: every
+//      index bit below K moves to its mode's field (a byte table), the block
+//      key is the index above bit K, and the values follow the permutation;
 //   4. runs of equal block key (flags and a select), copied to the host, where
 //      the block list, per-run high bits and tile table are finished by the
 //      same code as the host builder;
-//   5. the frequent rows of each mode (sampled counts, a descending radix sort).
+//   5. the frequent rows of each mode (sampled rows sorted and run-length
+//      counted, then a descending radix sort of the counts).
 // The result equals blco_build's bit for bit.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
@@ -84,37 +86,38 @@ __global__ __launch_bounds__(256) void k_gather_u64(const uint64_t* __restrict__
   if (i < n) dst[i] = src[idx[i]];
 }
 
-// Keys, values and block keys in sorted order; start flags of runs.
-__global__ __launch_bounds__(256) void k_encode(LinParams p, int64_t n,
+// Keys, values and block keys in sorted order, from the sorted index (slo:
+// bits 0..63, shi: bits 64..127 or NULL): the key gathers every index bit
+// below K into its mode's field through a byte table (enc[k][v]: key bits of
+// byte k holding v); the block key is the index above bit K.
+constexpr int kEncBytes = 8;   // K <= 64
+__global__ __launch_bounds__(256) void k_encode(int64_t n, int K, const uint64_t* __restrict__ enc,
+                                                const uint64_t* __restrict__ slo,
+                                                const uint64_t* __restrict__ shi,
                                                 const uint32_t* __restrict__ perm,
-                                                const uint64_t* __restrict__ lo,
-                                                const uint64_t* __restrict__ hi,
                                                 const float* __restrict__ vals,
                                                 uint64_t* __restrict__ keys,
                                                 float* __restrict__ vout,
                                                 uint64_t* __restrict__ bkey) {
+  __shared__ uint64_t s_enc[kEncBytes * 256];
+  for (int i = threadIdx.x; i < kEncBytes * 256; i += 256) s_enc[i] = enc[i];
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const uint32_t src = perm[i];
+  const uint64_t l = slo[i], h = shi ? shi[i] : 0;
+  const uint64_t low = K >= 64 ? l : (l & ((1ULL << K) - 1));
   uint64_t key = 0;
-  for (int m = 0; m < p.N; ++m) {
-    const uint64_t c = p.coords[m][src];
-    const uint64_t mask = p.w[m] >= 64 ? ~0ULL : ((1ULL << p.w[m]) - 1);
-    key |= (c & mask) << p.s[m];
-  }
+#pragma unroll
+  for (int k = 0; k < kEncBytes; ++k) key |= s_enc[k * 256 + ((low >> (8 * k)) & 255)];
   keys[i] = key;
-  vout[i] = vals[src];
-  // block key: the index above bit K
-  const uint64_t l = lo[src], h = hi ? hi[src] : 0;
+  vout[i] = vals[perm[i]];
   uint64_t B;
-  if (p.K >= 128)
-    B = 0;
-  else if (p.K >= 64)
-    B = h >> (p.K - 64);
-  else if (p.K == 0)
+  if (K >= 64)
+    B = h >> (K - 64);
+  else if (K == 0)
     B = l;
   else
-    B = (l >> p.K) | (h << (64 - p.K));
+    B = (l >> K) | (h << (64 - K));
   bkey[i] = B;
 }
 
@@ -131,24 +134,13 @@ __global__ __launch_bounds__(256) void k_gather_keys(const uint64_t* __restrict_
   if (r < nruns) out[r] = bkey[starts[r]];
 }
 
-__global__ __launch_bounds__(256) void k_count_sampled(const uint32_t* __restrict__ c, int64_t n,
-                                                       int64_t step, uint32_t* __restrict__ cnt) {
+__global__ __launch_bounds__(256) void k_sample(const uint32_t* __restrict__ c, int64_t samples,
+                                                int64_t step, uint32_t* __restrict__ out) {
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t i = s * step;
-  if (i < n) atomicAdd(&cnt[c[i]], 1u);
-}
-
-__global__ __launch_bounds__(256) void k_iota_u32(uint32_t* __restrict__ a, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) a[i] = (uint32_t)i;
+  if (s < samples) out[s] = c[s * step];
 }
 
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v) { *p = v; }
-
-__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* __restrict__ a, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) a[i] = 0;
-}
 
 unsigned grid_of(int64_t n) { return (unsigned)std::max<int64_t>((n + 255) / 256, 1); }
 
@@ -194,9 +186,10 @@ void release_tensor_arrays(blco_tensor* t) {
 
 void pinned_release(void* p) { (void)hipHostFree(p); }
 
-// Frequent rows of every mode, as find_hot_rows: counts over every step-th
-// non-zero, the kHotMax + 1 most frequent rows (ties by row), the frequent
-// ones reaching the threshold.
+// Frequent rows of every mode, as find_hot_rows: the rows of every step-th
+// non-zero are sorted and run-length counted (no atomics: hot rows would
+// serialise), then the kHotMax + 1 most frequent (ties by row, as the stable
+// sort keeps ascending rows) are kept and those reaching the threshold marked.
 int gpu_hot_rows(const LinParams& lp, int64_t nnz, int64_t min_count, Pool& pool, hipStream_t s,
                  blco_tensor* t) {
   const int N = lp.N;
@@ -208,32 +201,51 @@ int gpu_hot_rows(const LinParams& lp, int64_t nnz, int64_t min_count, Pool& pool
   const int64_t samples = (nnz + step - 1) / step;
   const uint64_t need = (uint64_t)std::max<int64_t>(1, (min_count + step - 1) / step);
   int rc;
+  uint32_t *smp, *sorted, *uniq, *cnt, *cnt2, *row2;
+  int64_t* nuniq;
+  if ((rc = pool.get(&smp, samples)) || (rc = pool.get(&sorted, samples)) ||
+      (rc = pool.get(&uniq, samples)) || (rc = pool.get(&cnt, samples)) ||
+      (rc = pool.get(&cnt2, samples)) || (rc = pool.get(&row2, samples)) || (rc = pool.get(&nuniq, 1)))
+    return rc;
+  void* tmp = nullptr;
+  size_t tmp_cap = 0;
+  auto need_tmp = [&](size_t bytes) -> int {
+    if (bytes <= tmp_cap) return BLCO_OK;
+    int r = pool.get((char**)&tmp, bytes);
+    if (r == BLCO_OK) tmp_cap = bytes;
+    return r;
+  };
   for (int n = 0; n < N; ++n) {
     const uint64_t I = lp.dims[n];
     if (I > ((uint64_t)1 << 26)) continue;
-    uint32_t *cnt, *cnt2, *row, *row2;
-    if ((rc = pool.get(&cnt, I)) || (rc = pool.get(&cnt2, I)) || (rc = pool.get(&row, I)) ||
-        (rc = pool.get(&row2, I)))
-      return rc;
-    hipLaunchKernelGGL(k_zero_u32, dim3(grid_of((int64_t)I)), dim3(256), 0, s, cnt, (int64_t)I);
-    hipLaunchKernelGGL(k_count_sampled, dim3(grid_of(samples)), dim3(256), 0, s, lp.coords[n],
-                       nnz, step, cnt);
-    hipLaunchKernelGGL(k_iota_u32, dim3(grid_of((int64_t)I)), dim3(256), 0, s, row, (int64_t)I);
+    const int bits = std::max(1, lp.b[n]);
+    hipLaunchKernelGGL(k_sample, dim3(grid_of(samples)), dim3(256), 0, s, lp.coords[n], samples,
+                       step, smp);
     HIPCHK(hipGetLastError());
-    size_t tmp_bytes = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp_bytes, cnt, cnt2, row, row2,
-                                                        (int)I, 0, 32, s));
-    void* tmp;
-    if ((rc = pool.get((char**)&tmp, tmp_bytes))) return rc;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tmp_bytes, cnt, cnt2, row, row2,
-                                                        (int)I, 0, 32, s));
-    const size_t k = std::min<size_t>((size_t)I, kHotMax + 1);
-    std::vector<uint32_t> hc(k), hr(k);
-    HIPCHK(hipMemcpyAsync(hc.data(), cnt2, k * 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hr.data(), row2, k * 4, hipMemcpyDeviceToHost, s));
+    size_t b1 = 0, b2 = 0, b3 = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, b1, smp, sorted, (int)samples, 0, bits, s));
+    HIPCHK(hipcub::DeviceRunLengthEncode::Encode(nullptr, b2, sorted, uniq, cnt, nuniq,
+                                                 (int)samples, s));
+    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, b3, cnt, cnt2, uniq, row2,
+                                                        (int)samples, 0, 32, s));
+    if ((rc = need_tmp(std::max(b1, std::max(b2, b3))))) return rc;
+    HIPCHK(hipcub::DeviceRadixSort::SortKeys(tmp, b1, smp, sorted, (int)samples, 0, bits, s));
+    HIPCHK(hipcub::DeviceRunLengthEncode::Encode(tmp, b2, sorted, uniq, cnt, nuniq, (int)samples,
+                                                 s));
+    int64_t nu = 0;
+    HIPCHK(hipMemcpyAsync(&nu, nuniq, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, b3, cnt, cnt2, uniq, row2, (int)nu, 0,
+                                                        32, s));
+    const size_t k = std::min<size_t>((size_t)nu, kHotMax + 1);
+    std::vector<uint32_t> hc(k), hr(k);
+    if (k) {
+      HIPCHK(hipMemcpyAsync(hc.data(), cnt2, k * 4, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hr.data(), row2, k * 4, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
     int nh = 0;
-    for (size_t j = 0; j < k && hc[j] > 0; ++j) {
+    for (size_t j = 0; j < k; ++j) {
       t->hot_cnt[(size_t)n * (kHotMax + 1) + j] = (uint64_t)hc[j] * (uint64_t)step;
       if (j < (size_t)kHotMax && hc[j] >= need) t->hot[(size_t)n * kHotMax + nh++] = hr[j];
     }
@@ -293,38 +305,63 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
     return set_error(BLCO_ERANGE, "coordinate out of range at non-zero %lld", (long long)i);
   }
   // 2. stable sort along the encoding line
+  uint64_t* hi_sorted = nullptr;
   if (nnz > 0) {
     const int nb0 = std::max(1, std::min(L.T, 64));
     size_t tmp_bytes = 0, t2 = 0;
     HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, lo, lo2, idx, perm, (int)nnz, 0,
                                               nb0, s));
-    if (wide)
-      HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, t2, hi2, hi, perm, perm2, (int)nnz, 0,
-                                                L.T - 64, s));
+    if (wide) {
+      if ((rc = pool.get(&hi_sorted, nnz))) return rc;
+      HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, t2, hi2, hi_sorted, perm, perm2, (int)nnz,
+                                                0, L.T - 64, s));
+    }
     void* tmp;
     if ((rc = pool.get((char**)&tmp, std::max(tmp_bytes, t2)))) return rc;
     HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, lo, lo2, idx, perm, (int)nnz, 0, nb0,
                                               s));
     if (wide) {
-      // the high bits in that order, then a stable pass over them (the
-      // original lo and hi stay in place for the re-encoding)
+      // the high bits in that order, a stable pass over them, then the low
+      // bits in the final order
       hipLaunchKernelGGL(k_gather_u64, dim3(grid_of(nnz)), dim3(256), 0, s, hi, perm, nnz, hi2);
       HIPCHK(hipGetLastError());
-      uint64_t* hi_sorted;
-      if ((rc = pool.get(&hi_sorted, nnz))) return rc;
       HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp, t2, hi2, hi_sorted, perm, perm2, (int)nnz, 0,
                                                 L.T - 64, s));
       std::swap(perm, perm2);
+      hipLaunchKernelGGL(k_gather_u64, dim3(grid_of(nnz)), dim3(256), 0, s, lo, perm, nnz, lo2);
+      HIPCHK(hipGetLastError());
     }
   }
   // 3. re-encode in sorted order; keys and values go straight into the tensor
+  std::vector<uint64_t> enc((size_t)kEncBytes * 256, 0);
+  {
+    int owner_mode[128], owner_bit[128];
+    for (int m = 0; m < L.N; ++m)
+      for (int j = 0; j < L.b[m]; ++j) {
+        owner_mode[L.pos[m][j]] = m;
+        owner_bit[L.pos[m][j]] = j;
+      }
+    for (int k = 0; k < kEncBytes; ++k)
+      for (int v = 0; v < 256; ++v) {
+        uint64_t x = 0;
+        for (int j = 0; j < 8; ++j) {
+          const int q = 8 * k + j;
+          if (!((v >> j) & 1) || q >= L.K) continue;
+          x |= 1ULL << (L.s[owner_mode[q]] + owner_bit[q]);
+        }
+        enc[(size_t)k * 256 + v] = x;
+      }
+  }
+  uint64_t* d_enc;
+  if ((rc = pool.get(&d_enc, enc.size()))) return rc;
+  HIPCHK(hipMemcpyAsync(d_enc, enc.data(), enc.size() * 8, hipMemcpyHostToDevice, s));
   size_t acc = 0;
   HIPCHK(hipMalloc((void**)&t->d_keys, sizeof(uint64_t) * std::max<int64_t>(nnz, 1)));
   HIPCHK(hipMalloc((void**)&t->d_vals, sizeof(float) * std::max<int64_t>(nnz, 1)));
   acc += (sizeof(uint64_t) + sizeof(float)) * (size_t)std::max<int64_t>(nnz, 1);
   if (nnz > 0) {
-    hipLaunchKernelGGL(k_encode, dim3(grid_of(nnz)), dim3(256), 0, s, lp, nnz, perm, lo, hi, values,
-                       t->d_keys, t->d_vals, bkey);
+    hipLaunchKernelGGL(k_encode, dim3(grid_of(nnz)), dim3(256), 0, s, nnz, L.K, d_enc, lo2,
+                       hi_sorted, perm, values, t->d_keys, t->d_vals, bkey);
     HIPCHK(hipGetLastError());
   }
   // 4. runs of equal block key
