@@ -3,8 +3,8 @@
 //
 // Steps, each a kernel or a device-wide primitive on the caller's stream:
 //   1. ALTO linearization of every coordinate (Section 4.1): bit j of mode n
-//      goes to position pos[n][j] of a 64- or 128-bit index; out-of-range
-//      coordinates are flagged;
+//      goes to position pos[n][j] of a 64- or 128-bit index (per-byte deposit
+//      tables); out-of-range coordinates are flagged;
 //   2. a stable radix sort of (index, non-zero number) pairs: one pass over the
 //      low 64 bits, then, for indices over 64 bits, one over the high bits of
 //      the indices gathered in that order (least significant digits first);
@@ -52,7 +52,11 @@ struct LinParams {
 
 // ALTO index of every non-zero (lo: bits 0..63, hi: bits 64..127) and its
 // number; *bad = smallest non-zero number with a coordinate out of range.
-__global__ __launch_bounds__(256) void k_linearize(LinParams p, int64_t n, uint64_t* __restrict__ lo,
+// dep[((m * 4 + k) * 256 + v) * 2 + {0, 1}]: the (lo, hi) index bits of byte k
+// of a mode-m coordinate holding v.
+__global__ __launch_bounds__(256) void k_linearize(LinParams p, int64_t n,
+                                                   const uint64_t* __restrict__ dep,
+                                                   uint64_t* __restrict__ lo,
                                                    uint64_t* __restrict__ hi,
                                                    uint32_t* __restrict__ idx,
                                                    unsigned long long* __restrict__ bad) {
@@ -65,13 +69,12 @@ __global__ __launch_bounds__(256) void k_linearize(LinParams p, int64_t n, uint6
       atomicMin(bad, (unsigned long long)i);
       c = 0;
     }
-    for (int j = 0; j < p.b[m]; ++j) {
-      const uint64_t bit = (c >> j) & 1u;
-      const int q = p.pos[m][j];
-      if (q < 64)
-        l |= bit << q;
-      else
-        h |= bit << (q - 64);
+    const uint64_t* d = dep + (size_t)m * 4 * 256 * 2;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t v = (c >> (8 * k)) & 255u;
+      l |= d[(k * 256 + v) * 2];
+      h |= d[(k * 256 + v) * 2 + 1];
     }
   }
   lo[i] = l;
@@ -285,10 +288,31 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
     return rc;
   if (wide && ((rc = pool.get(&hi, nnz)) || (rc = pool.get(&hi2, nnz)) || (rc = pool.get(&perm2, nnz))))
     return rc;
-  // 1. linearize
+  // 1. linearize, through per-byte deposit tables
+  std::vector<uint64_t> dep((size_t)L.N * 4 * 256 * 2, 0);
+  for (int m = 0; m < L.N; ++m)
+    for (int k = 0; k < 4; ++k)
+      for (int v = 0; v < 256; ++v) {
+        uint64_t xl = 0, xh = 0;
+        for (int j = 0; j < 8; ++j) {
+          const int bj = 8 * k + j;
+          if (!((v >> j) & 1) || bj >= L.b[m]) continue;
+          const int q = L.pos[m][bj];
+          if (q < 64)
+            xl |= 1ULL << q;
+          else
+            xh |= 1ULL << (q - 64);
+        }
+        dep[(((size_t)m * 4 + k) * 256 + v) * 2] = xl;
+        dep[(((size_t)m * 4 + k) * 256 + v) * 2 + 1] = xh;
+      }
+  uint64_t* d_dep;
+  if ((rc = pool.get(&d_dep, dep.size()))) return rc;
+  HIPCHK(hipMemcpyAsync(d_dep, dep.data(), dep.size() * 8, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s, bad, ~0ULL);
   if (nnz > 0)
-    hipLaunchKernelGGL(k_linearize, dim3(grid_of(nnz)), dim3(256), 0, s, lp, nnz, lo, hi, idx, bad);
+    hipLaunchKernelGGL(k_linearize, dim3(grid_of(nnz)), dim3(256), 0, s, lp, nnz, d_dep, lo, hi,
+                       idx, bad);
   HIPCHK(hipGetLastError());
   unsigned long long first_bad = ~0ULL;
   HIPCHK(hipMemcpyAsync(&first_bad, bad, 8, hipMemcpyDeviceToHost, s));
