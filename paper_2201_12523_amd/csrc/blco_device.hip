@@ -1048,15 +1048,21 @@ __global__ __launch_bounds__(kSB) void k_mttkrp_stash(KParams p, StashCfg cfg) {
   }
 }
 
-// Sampled reconstruction at the non-zeros, residual and fp64 partial sums of
-// the squared residual (CP model, Section 2.2).  One wave per tile; in the
-// computing phase a group of LPN lanes spans the rank of one non-zero.
-template <int LPN, typename FT, int N>
+// Sampled CP model, residual and squared residual sums (Section 2.2 model):
+// one wave per 64 consecutive non-zeros.  Each non-zero's record (byte offsets,
+// or row indices when BIG, of its N factor rows, and its value) goes to LDS;
+// groups of 16 lanes (RPL ranks per lane) then walk 16 records each,
+// 8 / RPL at a time, issuing every gather of those records before the first
+// use, and reduce the rank sum across the group.  The residual x - xhat is
+// written in BLCO order; the squared residuals are summed in fp64 per
+// workgroup (k_reduce_loss adds the partials in a fixed order).
+template <int RPL, typename FT, int N, bool BIG>
 __global__ __launch_bounds__(kBlock) void k_loss_tile(KParams p) {
-  constexpr int G = 64 / LPN;
-  constexpr int PPG = 64 / G;
+  constexpr int LPN = 16;
+  constexpr int G = 64 / LPN;                  // groups per wave
+  constexpr int PPG = 64 / G;                  // records per group
   constexpr int NF = N + 1;
-  constexpr int U = PPG < 4 ? PPG : 4;
+  constexpr int U = (8 / RPL) < PPG ? (8 / RPL) : PPG;
   __shared__ uint32_t s[kWaves][64][NF];
   __shared__ float s_e[kWaves][64];
   __shared__ double s_part[kWaves];
@@ -1076,32 +1082,58 @@ __global__ __launch_bounds__(kBlock) void k_loss_tile(KParams p) {
     for (int m = 0; m < N; ++m) c[m] = 0;
   }
 #pragma unroll
-  for (int m = 0; m < N; ++m) s[wv][lane][m] = c[m];
+  for (int m = 0; m < N; ++m) s[wv][lane][m] = BIG ? c[m] : c[m] * p.rowbytes;
   s[wv][lane][N] = __float_as_uint(x);
+  s_e[wv][lane] = x;
+  __amdgpu_buffer_rsrc_t rs[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m)
+    rs[m] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.A[m]), 0, (int)p.abytes[m],
+                                              (int)kBufFlags);
   wave_sync_lds();
   const int g = lane / LPN;
   const int rl = lane % LPN;
   const int R = p.R;
-  for (int q0 = 0; q0 < PPG; q0 += U) {
-    float part[U];
+  for (int r0 = 0; r0 < R; r0 += LPN * RPL) {
+    uint32_t loff[RPL];
+    bool ract[RPL];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t* e = s[wv][g * PPG + q0 + u];
-      float acc = 0.f;
-      for (int r = rl; r < R; r += LPN) {
-        float v = 1.f;
-#pragma unroll
-        for (int m = 0; m < N; ++m) v *= ld_factor<FT>(p.A[m], (size_t)e[m] * R + r);
-        acc += v;
-      }
-      part[u] = acc;
+    for (int q = 0; q < RPL; ++q) {
+      const int r = r0 + rl + q * LPN;
+      ract[q] = r < R;
+      loff[q] = (uint32_t)(ract[q] ? r : 0) * (uint32_t)sizeof(FT);
     }
+    for (int q0 = 0; q0 < PPG; q0 += U) {
+      float v[U][RPL];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < U; ++u) {
+        const uint32_t* e = s[wv][g * PPG + q0 + u];
 #pragma unroll
-      for (int off = LPN / 2; off > 0; off >>= 1) part[u] += __shfl_xor(part[u], off);
-      const int pidx = g * PPG + q0 + u;
-      if (rl == 0) s_e[wv][pidx] = __uint_as_float(s[wv][pidx][N]) - part[u];
+        for (int q = 0; q < RPL; ++q) v[u][q] = 1.f;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+          const uint32_t f = e[m];
+          if constexpr (BIG) {
+            const FT* rowp = static_cast<const FT*>(p.A[m]) + (size_t)f * R;
+#pragma unroll
+            for (int q = 0; q < RPL; ++q)
+              v[u][q] *= ld_factor<FT>(rowp, (size_t)(loff[q] / sizeof(FT)));
+          } else {
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) v[u][q] *= ld_buf<FT>(rs[m], f + loff[q]);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        float part = 0.f;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q)
+          if (ract[q]) part += v[u][q];
+#pragma unroll
+        for (int off = LPN / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        if (rl == 0) s_e[wv][g * PPG + q0 + u] -= part;
+      }
     }
   }
   wave_sync_lds();
@@ -1268,17 +1300,17 @@ static StashFn pick_stash(int N) {
   }
 }
 
-template <int LPN, typename FT>
+template <int RPL, typename FT, bool BIG>
 static KernelFn pick_loss(int N) {
   switch (N) {
-    case 1: return k_loss_tile<LPN, FT, 1>;
-    case 2: return k_loss_tile<LPN, FT, 2>;
-    case 3: return k_loss_tile<LPN, FT, 3>;
-    case 4: return k_loss_tile<LPN, FT, 4>;
-    case 5: return k_loss_tile<LPN, FT, 5>;
-    case 6: return k_loss_tile<LPN, FT, 6>;
-    case 7: return k_loss_tile<LPN, FT, 7>;
-    default: return k_loss_tile<LPN, FT, 8>;
+    case 1: return k_loss_tile<RPL, FT, 1, BIG>;
+    case 2: return k_loss_tile<RPL, FT, 2, BIG>;
+    case 3: return k_loss_tile<RPL, FT, 3, BIG>;
+    case 4: return k_loss_tile<RPL, FT, 4, BIG>;
+    case 5: return k_loss_tile<RPL, FT, 5, BIG>;
+    case 6: return k_loss_tile<RPL, FT, 6, BIG>;
+    case 7: return k_loss_tile<RPL, FT, 7, BIG>;
+    default: return k_loss_tile<RPL, FT, 8, BIG>;
   }
 }
 
@@ -1328,16 +1360,17 @@ static KernelFn select_win(int N, int R, int fdt, bool big, bool stash) {
   return big ? select_win_t<uint16_t, true>(N, R, stash) : select_win_t<uint16_t, false>(N, R, stash);
 }
 
-static KernelFn select_loss(int N, int R, int fdt) {
-  int lpn = lanes_per_nnz(R);
-  if (fdt == BLCO_F32) {
-    if (lpn == 16) return pick_loss<16, float>(N);
-    if (lpn == 32) return pick_loss<32, float>(N);
-    return pick_loss<64, float>(N);
-  }
-  if (lpn == 16) return pick_loss<16, uint16_t>(N);
-  if (lpn == 32) return pick_loss<32, uint16_t>(N);
-  return pick_loss<64, uint16_t>(N);
+template <typename FT, bool BIG>
+static KernelFn select_loss_t(int N, int R) {
+  if (R <= 16) return pick_loss<1, FT, BIG>(N);
+  if (R <= 32) return pick_loss<2, FT, BIG>(N);
+  return pick_loss<4, FT, BIG>(N);
+}
+
+static KernelFn select_loss(int N, int R, int fdt, bool big) {
+  if (fdt == BLCO_F32)
+    return big ? select_loss_t<float, true>(N, R) : select_loss_t<float, false>(N, R);
+  return big ? select_loss_t<uint16_t, true>(N, R) : select_loss_t<uint16_t, false>(N, R);
 }
 
 // MTTKRP kernel variant, chosen once per process from BLCO_KERNEL:
@@ -1960,7 +1993,17 @@ extern "C" int blco_sampled_loss(blco_tensor* t, const void* const* factors, int
   p.partials = t->d_partials;
   p.R = rank;
   p.mode = -1;
-  KernelFn f = select_loss(t->lay.N, rank, factor_dtype);
+  // factors below 4 GiB are gathered with 32-bit byte offsets, larger ones
+  // with 64-bit addresses
+  const size_t fsz = factor_elem_bytes(factor_dtype);
+  p.rowbytes = (uint32_t)((size_t)rank * fsz);
+  bool big = (size_t)rank * fsz >= (1ULL << 31);
+  for (int m = 0; m < t->lay.N; ++m) {
+    const size_t bytes = (size_t)t->lay.dims[m] * rank * fsz;
+    p.abytes[m] = (uint32_t)std::min<size_t>(bytes, 0xFFFFFFFFull);
+    if (bytes > 0xFFFFFFFFull) big = true;
+  }
+  KernelFn f = select_loss(t->lay.N, rank, factor_dtype, big);
   hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(kBlock), 0, s, p);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(1024), 0, s, (const double*)t->d_partials,
