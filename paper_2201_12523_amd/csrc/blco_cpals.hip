@@ -2,7 +2,8 @@
 //
 // Per iteration and mode n: V = Hadamard product of the Gram matrices of the
 // other factors, M = mode-n MTTKRP, A^(n) = M V^+.  The small dense steps run
-// in their own kernels: Gram matrices (fp32 products, fp64 sums), the R x R
+// in their own kernels: Gram matrices (fp32 products, fp64 sums; on the
+// matrix cores for R <= 32), the R x R
 // pseudo-inverse of V in one workgroup (fp64), the row-wise product M V^+
 // (fp64 sums), and the fit.  The MTTKRP is the library's (blco_mttkrp).
 #include <hip/hip_runtime.h>
@@ -89,6 +90,57 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const FT* __restrict__ A,
   for (int e = 0; e < E; ++e) {
     const int ent = tid + e * kGramThreads;
     if (ent < RR && lo < hi) atomicAdd(&G[ent], acc[e]);
+  }
+}
+
+// G += A^T A for R <= 32 on the matrix cores: each wave takes a contiguous
+// range of rows and, two rows per step, feeds the 2 x 32 tile X of those rows
+// to v_mfma_f32_32x32x2f32 as both operands (A-operand X^T, B-operand X: lane l
+// holds X[l / 32][l % 32] for both), accumulating the 32 x 32 product in fp32;
+// every kGramFlush rows the accumulators are added into fp64 registers, and
+// at the end each wave adds its fp64 sums into G with fp64 atomics.  Output
+// layout of the instruction: register v of lane l holds row
+// 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
+constexpr int kGramFlush = 64;   // rows summed in fp32 before moving to fp64
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <typename FT>
+__global__ __launch_bounds__(256) void k_gram_mfma(const FT* __restrict__ A, int64_t rows, int R,
+                                                   int64_t per_wave, double* __restrict__ G) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t lo = wave * per_wave;
+  const int64_t hi = min(rows, lo + per_wave);
+  if (lo >= hi) return;
+  const int col = lane & 31;
+  const int kk = lane >> 5;
+  const bool cact = col < R;
+  double acc64[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc64[v] = 0.0;
+  for (int64_t r0 = lo; r0 < hi; r0 += kGramFlush) {
+    const int64_t r1 = min(hi, r0 + kGramFlush);
+    floatx16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+    constexpr int S = 8;   // row pairs loaded before the first use
+    for (int64_t r = r0; r < r1; r += 2 * S) {
+      float x[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        const int64_t row = r + 2 * q + kk;
+        x[q] = (cact && row < r1) ? ld_elem<FT>(A, row * R + col) : 0.f;
+      }
+#pragma unroll
+      for (int q = 0; q < S; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], x[q], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc64[v] += (double)acc[v];
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = 8 * (v >> 2) + 4 * kk + (v & 3);
+    if (i < R && cact) atomicAdd(&G[i * R + col], acc64[v]);
   }
 }
 
@@ -296,6 +348,21 @@ int launch_gram(const void* A, int dtype, int64_t rows, int R, double* G, hipStr
   hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, s, G, R * R);
   HIPCHK(hipGetLastError());
   if (rows <= 0) return BLCO_OK;
+  if (R <= 32) {
+    // matrix cores: about 2048 waves, each over at least one flush block of rows
+    int64_t per = std::max<int64_t>((rows + 2047) / 2048, kGramFlush);
+    per = (per + kGramFlush - 1) / kGramFlush * kGramFlush;
+    const int64_t waves = (rows + per - 1) / per;
+    const int64_t nwg = (waves + 3) / 4;
+    if (dtype == BLCO_BF16)
+      hipLaunchKernelGGL(k_gram_mfma<uint16_t>, dim3((unsigned)nwg), dim3(256), 0, s,
+                         static_cast<const uint16_t*>(A), rows, R, per, G);
+    else
+      hipLaunchKernelGGL(k_gram_mfma<float>, dim3((unsigned)nwg), dim3(256), 0, s,
+                         static_cast<const float*>(A), rows, R, per, G);
+    HIPCHK(hipGetLastError());
+    return BLCO_OK;
+  }
   const int64_t want = 512;
   int64_t per = std::max<int64_t>((rows + want - 1) / want, kGramRows);
   const int64_t nwg = (rows + per - 1) / per;
