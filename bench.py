@@ -562,6 +562,37 @@ def summarize_pmc(fetch_csv, write_csv, copy_bytes, kernel=None, out=TRAFFIC_FIL
     print("\n".join(lines))
 
 
+def summarize_counters(workload, kernel, nnz, out, *csvs):
+    """Per-launch and per-non-zero means of every counter in one or more rocprofv3
+    --pmc CSVs, over the dispatches of one kernel (instruction counts, LDS bank
+    conflicts, and the atomics the kernel sends to the L2 and on to memory)."""
+    import csv
+
+    lines = [f"# rocprofv3 counters of {kernel}, workload {workload}, {nnz} non-zeros per launch",
+             "# (one mode per launch; mean over the kernel's dispatches). Commands, one per pass:"]
+    vals, ndisp = {}, {}
+    for path in csvs:
+        names = set()
+        for r in csv.DictReader(open(path)):
+            if not r["Kernel_Name"].startswith("void " + kernel + "("):
+                continue
+            names.add(r["Counter_Name"])
+            vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        for c in names:
+            ndisp[c] = len(vals[c])
+        lines.append(f"#   rocprofv3 --pmc {' '.join(sorted(names))} -o run --output-format csv "
+                     f"-- python3 bench.py --workload {workload} --steps 2 --warmup 0 "
+                     "--no-cpu-baseline")
+    lines.append(f"kernel_source_sha256_16: {kernel_source_hash()}")
+    lines.append(f"{'counter':40s} {'dispatches':>10s} {'per_launch':>16s} {'per_nnz':>10s}")
+    for c in sorted(vals):
+        m = float(np.mean(vals[c]))
+        lines.append(f"{c:40s} {ndisp[c]:10d} {m:16.1f} {m / nnz:10.4f}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def resolution_sweep(args, torch, blco, synth):
     """Both conflict-resolution mechanisms (Sections 5.1-5.2) on the short mode of
     3-mode 2^21 x 2^17 x I tensors (Zipf(1.1) long modes, uniform short mode),
@@ -598,6 +629,10 @@ def resolution_sweep(args, torch, blco, synth):
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
         summarize_pmc(sys.argv[2], sys.argv[3], int(sys.argv[4]))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
+        # WORKLOAD KERNEL NNZ OUT CSV...
+        summarize_counters(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5], *sys.argv[6:])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
