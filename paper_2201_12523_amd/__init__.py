@@ -81,7 +81,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_SO):
-            raise RuntimeError(f"{_SO} is missing: build it with `python -m paper_2201_12523_amd.build`")
+            raise RuntimeError(f"{_SO} is missing: build it with `python -m paper_2201_12523_amd.buildlib`")
         L = ctypes.CDLL(_SO)
         p, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
         L.blco_build.argtypes = [i32, p, i64, p, p, p, ctypes.POINTER(p)]

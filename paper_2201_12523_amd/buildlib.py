@@ -3,7 +3,7 @@
 Host builder (``csrc/blco_host.cpp``) with g++; device runtime and MTTKRP
 kernels (``csrc/blco_device.hip``), the CP-ALS driver (``csrc/blco_cpals.hip``) and
 the GPU builder (``csrc/blco_build_gpu.hip``) with hipcc; linked with hipcc.  Run as
-``python -m paper_2201_12523_amd.build``.
+``python -m paper_2201_12523_amd.buildlib``.
 """
 from __future__ import annotations
 
