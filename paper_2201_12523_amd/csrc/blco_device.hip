@@ -289,6 +289,49 @@ __device__ __forceinline__ void block_exclusive_scan(uint32_t* a, int tid, uint3
   __syncthreads();
 }
 
+// Lane q of this lane's 16-lane row (DPP row_newbcast), and the value of the
+// lane q places further along the row (DPP row_shl).  q must fold to a
+// constant where they are called (unrolled loops).
+__device__ __forceinline__ uint32_t row_bcast(uint32_t v, int q) {
+  switch (q) {
+    case 0: return __builtin_amdgcn_update_dpp(0u, v, 0x150, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_update_dpp(0u, v, 0x151, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0u, v, 0x152, 0xF, 0xF, false);
+    case 3: return __builtin_amdgcn_update_dpp(0u, v, 0x153, 0xF, 0xF, false);
+    case 4: return __builtin_amdgcn_update_dpp(0u, v, 0x154, 0xF, 0xF, false);
+    case 5: return __builtin_amdgcn_update_dpp(0u, v, 0x155, 0xF, 0xF, false);
+    case 6: return __builtin_amdgcn_update_dpp(0u, v, 0x156, 0xF, 0xF, false);
+    case 7: return __builtin_amdgcn_update_dpp(0u, v, 0x157, 0xF, 0xF, false);
+    case 8: return __builtin_amdgcn_update_dpp(0u, v, 0x158, 0xF, 0xF, false);
+    case 9: return __builtin_amdgcn_update_dpp(0u, v, 0x159, 0xF, 0xF, false);
+    case 10: return __builtin_amdgcn_update_dpp(0u, v, 0x15A, 0xF, 0xF, false);
+    case 11: return __builtin_amdgcn_update_dpp(0u, v, 0x15B, 0xF, 0xF, false);
+    case 12: return __builtin_amdgcn_update_dpp(0u, v, 0x15C, 0xF, 0xF, false);
+    case 13: return __builtin_amdgcn_update_dpp(0u, v, 0x15D, 0xF, 0xF, false);
+    case 14: return __builtin_amdgcn_update_dpp(0u, v, 0x15E, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_update_dpp(0u, v, 0x15F, 0xF, 0xF, false);
+  }
+}
+__device__ __forceinline__ uint32_t row_shl(uint32_t v, int q) {
+  switch (q) {
+    case 1: return __builtin_amdgcn_update_dpp(0u, v, 0x101, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0u, v, 0x102, 0xF, 0xF, false);
+    case 3: return __builtin_amdgcn_update_dpp(0u, v, 0x103, 0xF, 0xF, false);
+    case 4: return __builtin_amdgcn_update_dpp(0u, v, 0x104, 0xF, 0xF, false);
+    case 5: return __builtin_amdgcn_update_dpp(0u, v, 0x105, 0xF, 0xF, false);
+    case 6: return __builtin_amdgcn_update_dpp(0u, v, 0x106, 0xF, 0xF, false);
+    case 7: return __builtin_amdgcn_update_dpp(0u, v, 0x107, 0xF, 0xF, false);
+    case 8: return __builtin_amdgcn_update_dpp(0u, v, 0x108, 0xF, 0xF, false);
+    case 9: return __builtin_amdgcn_update_dpp(0u, v, 0x109, 0xF, 0xF, false);
+    case 10: return __builtin_amdgcn_update_dpp(0u, v, 0x10A, 0xF, 0xF, false);
+    case 11: return __builtin_amdgcn_update_dpp(0u, v, 0x10B, 0xF, 0xF, false);
+    case 12: return __builtin_amdgcn_update_dpp(0u, v, 0x10C, 0xF, 0xF, false);
+    case 13: return __builtin_amdgcn_update_dpp(0u, v, 0x10D, 0xF, 0xF, false);
+    case 14: return __builtin_amdgcn_update_dpp(0u, v, 0x10E, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_update_dpp(0u, v, 0x10F, 0xF, 0xF, false);
+  }
+}
+
 // target row of a record (field N - 1 of the record at LDS offset `at`)
 __device__ __forceinline__ uint32_t seg_target(const uint32_t* rec, int at, int mode, int N) {
   (void)mode;
@@ -344,7 +387,9 @@ __device__ __forceinline__ int hot_lookup(const uint32_t* keys, const uint32_t* 
 //     gets a record: byte offsets of the other modes' factor rows, target,
 //     value;
 //   computing: groups of LPN lanes (RPL ranks per lane) walk LPN consecutive
-//     grouped positions each, gathering factor rows with buffer loads and
+//     grouped positions each (records read from LDS, or for N = 3 held one
+//     per lane and passed along the group by DPP row broadcasts),
+//     gathering factor rows with buffer loads and
 //     summing the scaled Hadamard products in registers; a segment that ends
 //     inside the group is flushed once per rank; a segment that crosses into
 //     later groups is completed by the group it started in, from partial sums
@@ -495,7 +540,18 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
     const bool starts_before =
         p0 > 0 && p0 < nvalid && !((s_end[(p0 - 1) >> 6] >> ((p0 - 1) & 63)) & 1);
     const bool can_carry = p0 + PPG <= nvalid;
+    // 3-mode tensors with 16-lane groups (one DPP row per group): the walk
+    // takes record fields from registers.  Lane rl of a group starts with the
+    // record of the group's position rl; each step of U positions broadcasts
+    // lanes 0..U-1 of the row and then shifts the row down by U lanes.  (For
+    // other mode counts the extra registers cost more than the LDS reads save.)
+    constexpr bool kRowB = (LPN == 16) && (N == 3);
     for (int r0 = 0; r0 < R; r0 += LPN * RPL) {
+      uint32_t myrec[kRowB ? NF : 1];
+      if constexpr (kRowB) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) myrec[f] = s_rec[(p0 + rl) * NP + f];
+      }
       bool ract[RPL];
       uint32_t loff[RPL];
       float acc[RPL], carry[RPL];
@@ -512,13 +568,20 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
         float pr[U][RPL];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const uint32_t* e = &s_rec[(p0 + q0 + u) * NP];
-          const float xv = __uint_as_float(e[N]);
+          // the record of position q0 + u: from the row, or from LDS
+          uint32_t e[NF];
+#pragma unroll
+          for (int f = 0; f < NF; ++f)
+            if (f != N - 1) {
+              if constexpr (kRowB) e[f] = row_bcast(myrec[f], u);
+            }
+          const uint32_t* er = &s_rec[(p0 + q0 + u) * NP];
+          const float xv = __uint_as_float(kRowB ? e[N] : er[N]);
 #pragma unroll
           for (int k = 0; k < RPL; ++k) pr[u][k] = xv;
 #pragma unroll
           for (int j = 0; j + 1 < N; ++j) {
-            const uint32_t f = e[j];
+            const uint32_t f = kRowB ? e[j] : er[j];
             if constexpr (BIG) {
               const FT* rowp = static_cast<const FT*>(ap[j]) + (size_t)f * R;
 #pragma unroll
@@ -541,7 +604,8 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
 #pragma unroll
               for (int k = 0; k < RPL; ++k) s_head[tid * RPL + k] = acc[k];
             } else if (seg_end) {
-              const uint32_t tf = seg_target(s_rec, (p0 + q) * NP, p.mode, N);
+              const uint32_t tf = kRowB ? row_bcast(myrec[N - 1], u)
+                                        : seg_target(s_rec, (p0 + q) * NP, p.mode, N);
               if (K > 0 && (tf & kHotFlag)) {
                 float* srow = s_stash + (size_t)(tf & ~kHotFlag) * R + r0 + rl;
 #pragma unroll
@@ -562,6 +626,10 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
             for (int k = 0; k < RPL; ++k) acc[k] = 0.f;
             first = false;
           }
+        }
+        if constexpr (kRowB) {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) myrec[f] = row_shl(myrec[f], U);
         }
       }
       __syncthreads();
