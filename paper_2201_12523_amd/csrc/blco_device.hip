@@ -404,7 +404,11 @@ template <int LPN, int RPL, typename FT, int N, bool BIG, bool STASH>
 __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   constexpr int G = kWin / LPN;                 // groups of LPN lanes
   constexpr int PPG = kWin / G;                 // grouped positions per group (= LPN)
-  constexpr int U = PPG < (BLCO_WIN_U / RPL) ? PPG : (BLCO_WIN_U / RPL);
+  // positions whose gathers are issued together: BLCO_WIN_U / RPL, except for
+  // 3-mode tensors at one or four ranks per lane, where 4 and 1 positions keep
+  // the registers from spilling and measured 8% and 3% faster
+  constexpr int UW = (N == 3 && RPL == 1) ? 4 : (N == 3 && RPL == 4) ? 1 : BLCO_WIN_U / RPL;
+  constexpr int U = PPG < UW ? PPG : UW;
   constexpr int NF = N + 1;                     // record fields
   constexpr int NP = NF <= 4 ? 4 : ((NF + 1) / 2) * 2;
   __shared__ __align__(16) uint32_t s_rec[kWin * NP];  // records by grouped position
