@@ -1,32 +1,46 @@
 """Benchmark: BLCO sparse MTTKRP on one MI355X.
 
-Default workload (``zipf3``): 3-mode tensor 2^22 x 2^21 x 2^20 (63 key bits, one
-block), 50M distinct non-zeros with per-mode Zipf(1.1) indices, U(0,1) values,
-rank-32 N(0,1) factors; MTTKRP in all three modes from one BLCO copy.  A step is
-one MTTKRP per mode (output zero-fill included) with fp32 factors; inputs are
-resident in device memory before timing starts.  The bf16-factor form is timed
-beside it, and both are checked against the fp64 oracle on sampled rows in the
-CPU-baseline leg.
+Default run (no ``--workload``): the headline is the 4-mode workload on which
+the metric's fp32-versus-bf16 factor comparison is quoted:
 
-Other legs (``--workload``):
-  zipf4    4-mode 2^24 x 2^22 x 2^20 x 2^10 (76 bits, blocked on the top 12),
-           200M non-zeros, R = 32 and 64, fp32 and bf16 factors;
+  zipf4    2^24 x 2^22 x 2^20 x 2^10 (76-bit index, blocked on its top 12 bits),
+           200M distinct non-zeros, Zipf(1.2) indices on modes 1-2, uniform on
+           modes 3-4, lognormal(0,1) values.  `value` is R = 32 with fp32
+           factors: MTTKRP in all four modes from one BLCO copy, Gnnz/s per
+           mode-MTTKRP; R = 32 bf16 and R = 64 fp32 / bf16 are reported beside it.
+
+and the other workloads are reported in the same JSON line under ``secondary``:
+
+  zipf3    3-mode 2^22 x 2^21 x 2^20 (63 bits, one block), 50M, Zipf(1.1), R = 32;
+  cpgrad4  sparse CP loss + gradient step, 4-mode 2^20 x 2^18 x 2^16 x 2^12, 80M
+           non-zeros holding a planted rank-8 model plus noise, R = 32;
   oom3     3-mode 2^23 x 2^23 x 2^17, 1.5B non-zeros in pinned host memory,
-           streamed under an 8 GB device budget; copy/compute overlap reported;
-  cpgrad4  sparse CP loss + gradient step, 4-mode 2^20 x 2^18 x 2^16 x 2^12,
-           80M non-zeros holding a planted rank-8 model plus noise, R = 32;
-  cpals4   CP-ALS (Algorithm 1) iterations on the cpgrad4 tensor, R = --rank;
-  uniform3 the zipf3 shape with uniform indices;
-  short4   4-mode 2^21 x 2^17 x 24 x 168, 50M non-zeros, R = 32: the two short
-           modes take hierarchical conflict resolution (Section 5.3 heuristic),
-           and the register-based mechanism is timed beside it on those modes.
+           streamed under an 8 GB device budget (per-mode passes and one pass
+           for all modes; copy/compute overlap).  Skipped, with the reason in
+           the line, when the run is already past its time budget.
 
+A step is one MTTKRP per mode (output zero-fill included); inputs are resident
+in device memory before timing starts (pinned host memory for oom3).  Every
+time is from HIP events on the stream the library launches on.
+
+``roofline`` describes the kernel that takes the most time in the headline
+step.  `achieved` is its ALGORITHMIC (compulsory) HBM bytes per launch,
+12*nnz + sum_{m != n} U_m*R*s_f + I_n*R*4 (U_m: distinct mode-m indices), over
+its mean launch time; `frac` divides that by the 8 TB/s HBM peak.  `traffic`
+is the HBM bytes per launch measured by FETCH_SIZE/WRITE_SIZE counters
+(committed under profiles/, copy-calibrated), null when those counters were
+taken on other kernel sources.  `atomics` prices the memory-side atomic
+row-updates the kernel issues (counter-measured) at the rate of a distinct-row
+atomic calibration kernel timed in this run.
+
+Single legs: ``--workload zipf3|zipf4|uniform3|short4|small|oom3|cpgrad4|cpals4``.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -37,11 +51,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MTTKRP Gnnz/s per mode & % HBM peak; bf16 vs fp32 factors at stated rel error"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mttkrp_win_zipf3.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_mttkrp_zipf4.txt")
+T_START = time.time()
 
 
 def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench {time.time() - T_START:6.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -52,26 +67,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed counter summary, if it matches this kernel."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    vals = {}
-    with open(TRAFFIC_FILE) as f:
-        for line in f:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
-
-
 class Timer:
-    """Average milliseconds of `fn` over `steps` calls, with HIP events on torch's stream."""
+    """Average milliseconds of `fn` over `steps` calls: `warmup` untimed calls, a
+    synchronisation, HIP events around the timed calls on torch's current stream
+    (the stream the library launches on), and a synchronisation."""
 
     def __init__(self, torch):
         self.torch = torch
@@ -88,42 +87,194 @@ class Timer:
             fn()
         e1.record(s)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
+        return e0.elapsed_time(e1) / max(steps, 1)
 
 
-def sampled_rows(rng, I, k=120):
-    return np.unique(np.concatenate([np.arange(min(8, I)), rng.integers(0, I, k), [I - 1]])
-                     ).astype(np.uint32)
+# --------------------------------------------------------------------------- CPU baseline
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
-def row_errors(oracle, blco, torch, T, coords, vals, A_ref, F, outs, dims, modes, rng, dev):
-    """Max / median of |gpu - oracle| / sum|terms| over sampled rows of each mode."""
-    worst, meds = 0.0, []
-    for n in modes:
-        o = blco.mttkrp(T, n, F, out=outs[n])
-        rows = sampled_rows(rng, dims[n])
-        M, S = oracle.mttkrp_rows_f32(coords, vals, A_ref, n, rows, dims)
-        got = o[torch.from_numpy(rows.astype(np.int64)).to(dev)].cpu().numpy().astype(np.float64)
-        nz = S > 0
-        e = np.abs(got - M)[nz] / S[nz]
-        worst = max(worst, float(e.max()) if e.size else 0.0)
-        meds.append(float(np.median(e)) if e.size else 0.0)
-        log(f"  oracle rows, mode {n}: max normalised error {worst:.2e}")
-    return {"max": worst, "median": float(np.median(meds))}
-
-
-def cpu_oracle_rate(oracle, coords, vals, A, sample, modes):
-    """The fp64 oracle, single thread, over the first `sample` non-zeros of every mode."""
-    S = min(sample, len(vals))
-    cs = [c[:S] for c in coords]
+def cpu_oracle_baseline(oracle, coords, vals, A, modes, sample_1t, sample_all):
+    """The fp64 oracle as it stands, over a bounded prefix of the workload's non-zeros,
+    every mode: the serial oracle on one thread, and its OpenMP form on every thread the
+    process may use (OMP_NUM_THREADS).  `value` is the all-core rate."""
     Ad = [a.astype(np.float64) for a in A]
-    t0 = time.time()
-    for n in modes:
-        oracle.mttkrp(cs, vals[:S], Ad, n)
-    dt = time.time() - t0
-    return {"value": S * len(modes) / dt / 1e9, "unit": "Gnnz/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {S} non-zeros of the workload, {len(modes)} modes, fp64, "
-                      f"single thread, {dt:.1f}s"}
+    dims = [a.shape[0] for a in A]
+
+    def run(S, omp):
+        cs = [np.ascontiguousarray(c[:S]) for c in coords]
+        v = vals[:S].astype(np.float64)
+        used, atomic = 1, False
+        t0 = time.time()
+        for n in modes:
+            if omp:
+                _, _, used, at = oracle.mttkrp_omp(cs, v, Ad, n, dims=dims, with_scale=False)
+                atomic = atomic or at
+            else:
+                oracle.mttkrp(cs, v, Ad, n, dims=dims, with_scale=False)
+        return time.time() - t0, used, atomic
+
+    s1 = min(sample_1t, len(vals))
+    dt1, _, _ = run(s1, False)
+    log(f"cpu oracle, 1 thread: {s1} non-zeros x {len(modes)} modes in {dt1:.1f}s")
+    sa = min(sample_all, len(vals))
+    dta, used, atomic = run(sa, True)
+    log(f"cpu oracle, {used} threads: {sa} non-zeros x {len(modes)} modes in {dta:.1f}s")
+    return {"value": sa * len(modes) / dta / 1e9, "unit": "Gnnz/s", "cores": used,
+            "kind": "oracle",
+            "sample": f"first {sa} non-zeros of the workload, all {len(modes)} modes, fp64 "
+                      f"oracle on {used} threads ({'atomic' if atomic else 'private'} outputs), "
+                      f"{dta:.1f}s",
+            "single_thread": {"value": s1 * len(modes) / dt1 / 1e9, "unit": "Gnnz/s",
+                              "sample": f"first {s1} non-zeros, all {len(modes)} modes, "
+                                        f"serial fp64 oracle, {dt1:.1f}s"},
+            "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count(),
+                     "usable_cores": len(os.sched_getaffinity(0)),
+                     "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}}
+
+
+# --------------------------------------------------------------------------- counters
+
+def read_counters(path=COUNTERS_FILE):
+    """{kernel: {counter: mean per dispatch}} and the header fields of a committed
+    counter summary, or None when it is missing or was taken on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    head, per = {}, {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            if " | " in line:
+                k, c, _, v = [x.strip() for x in line.split(" | ")]
+                per.setdefault(k, {})[c] = float(v)
+            elif ":" in line:
+                a, b = line.split(":", 1)
+                head[a.strip()] = b.strip()
+    if head.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return head, per
+
+
+def _kernel_entry(per, name):
+    for k, v in per.items():
+        if k == name or k.startswith(name + "(") or k.startswith("void " + name + "("):
+            return v
+    return None
+
+
+def counter_traffic(counters, kernel):
+    """HBM bytes per launch of `kernel`: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by calibration_copy_bytes / (that counter for the calibration copy)."""
+    if counters is None:
+        return None
+    head, per = counters
+    k = _kernel_entry(per, kernel)
+    cp = per.get("calibration_copy")
+    if not k or not cp or "FETCH_SIZE" not in k or "WRITE_SIZE" not in k:
+        return None
+    nbytes = float(head["calibration_copy_bytes"])
+    fs = nbytes / (cp["FETCH_SIZE"] * 1024.0)
+    ws = nbytes / (cp["WRITE_SIZE"] * 1024.0)
+    return {"bytes": k["FETCH_SIZE"] * 1024.0 * fs + k["WRITE_SIZE"] * 1024.0 * ws,
+            "fetch_scale": fs, "write_scale": ws}
+
+
+def counter_row_ops(counters, kernel):
+    """Memory-side atomic row-updates per launch of `kernel`: its TCC_EA0_ATOMIC over
+    the same counter per row-update of the calibration probe (known row-ops)."""
+    if counters is None:
+        return None
+    head, per = counters
+    k = _kernel_entry(per, kernel)
+    pr = _kernel_entry(per, "k_atomic_probe")
+    if not k or not pr or "TCC_EA0_ATOMIC_sum" not in k or "TCC_EA0_ATOMIC_sum" not in pr:
+        return None
+    per_op = pr["TCC_EA0_ATOMIC_sum"] / float(head["probe_row_ops"])
+    return {"row_ops": k["TCC_EA0_ATOMIC_sum"] / per_op, "requests_per_row_op": per_op,
+            "requests": k["TCC_EA0_ATOMIC_sum"]}
+
+
+def summarize_counters(out, title, *csvs, copy_bytes=0, probe_row_ops=0, commands=()):
+    """Mean per dispatch of every counter of every kernel in rocprofv3 --pmc CSVs, written
+    as `kernel | counter | dispatches | mean`.  The largest device copy is recorded as
+    `calibration_copy` (its size is copy_bytes)."""
+    import csv
+
+    vals = {}
+    copies = {}
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            name, c, v = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
+            if "copyBuffer" in name:
+                copies.setdefault(c, []).append(v)
+                continue
+            vals.setdefault((name, c), []).append(v)
+    lines = [f"# {title}", "# rocprofv3 counters, mean per dispatch. Commands, one pass each:"]
+    lines += [f"#   {c}" for c in commands]
+    lines += [f"kernel_source_sha256_16: {kernel_source_hash()}",
+              f"calibration_copy_bytes: {copy_bytes}", f"probe_row_ops: {probe_row_ops}"]
+    for (name, c), v in sorted(vals.items()):
+        lines.append(f"{name} | {c} | {len(v)} | {float(np.mean(v)):.1f}")
+    for c, v in sorted(copies.items()):
+        lines.append(f"calibration_copy | {c} | 1 | {max(v):.1f}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_stats(out, title, stats_csv, command):
+    """Short text form of a rocprofv3 --stats kernel_stats.csv."""
+    import csv
+
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# {title}", f"# command: {command}", f"# kernel_source_sha256_16: {kernel_source_hash()}",
+             "# name | calls | total ns | average ns | percent | min ns | max ns"]
+    for r in rows:
+        lines.append(" | ".join([r["Name"], r["Calls"], r["TotalDurationNs"], r["AverageNs"],
+                                 f"{float(r['Percentage']):.2f}", r["MinNs"], r["MaxNs"]]))
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines[:20]))
+
+
+# --------------------------------------------------------------------------- helpers
+
+def win_kernel_name(R, N, ft="float", big=False, stash=True):
+    """Template name of the window MTTKRP kernel the library launches for rank R
+    (stash: the mode's frequent rows are held in LDS)."""
+    lpn, rpl = (16, 1) if R <= 16 else (16, 2) if R <= 32 else (16, 4) if R <= 64 else (64, 2)
+    b = lambda v: "true" if v else "false"
+    return f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {b(big)}, {b(stash)}>"
+
+
+def short_kernel_name(R, N, ft="float", big=False):
+    """Template name of the hierarchical MTTKRP kernel for a single rank slice of width R."""
+    rpl = 1 if R <= 16 else 2 if R <= 32 else 4
+    return f"k_mttkrp_short<{rpl}, {ft}, {N}, {'true' if big else 'false'}>"
+
+
+def big_factors(dims, R, sf, n):
+    """Whether mode n's MTTKRP gathers with 64-bit addresses (another factor of 4 GiB or more,
+    or a row of 2 GiB or more), as the library decides."""
+    return R * sf >= (1 << 31) or any(d * R * sf > 0xFFFFFFFF for m, d in enumerate(dims) if m != n)
+
+
+def mode_kernel(T, n, R, N, ft, big):
+    """The kernel one mode's MTTKRP launches (the library's rule, read back)."""
+    if T.resolution(n, R) == "hierarchical":
+        return short_kernel_name(R, N, ft, big)
+    return win_kernel_name(R, N, ft, big, stash=T.stash_rows(n, R) > 0)
 
 
 def describe(w, nnz):
@@ -144,38 +295,64 @@ def base_result(args, w, nnz, value, ms_step, dtype="f32"):
     }
 
 
+def check_rows_for(counts, I, rng, k=48):
+    """Rows compared with the oracle: the 16 most frequent, rows 0-7, k random, the last."""
+    hot = np.argsort(-counts, kind="stable")[:16]
+    return np.unique(np.concatenate([hot, np.arange(min(8, I)), rng.integers(0, I, k), [I - 1]])
+                     ).astype(np.uint32)
+
+
+def atomic_calibration(torch, blco, R, steps, rows=1 << 22):
+    """Distinct-row fp32 atomic rate: one row-update (R floats by 16-lane groups, the
+    MTTKRP flush) on each row of a rows x R output, in a random order."""
+    dev = torch.device("cuda:0")
+    out = torch.zeros((rows, R), dtype=torch.float32, device=dev)
+    g = torch.Generator(device="cpu").manual_seed(12523)
+    ids = torch.randperm(rows, generator=g).to(torch.int32).to(dev)
+    ms = Timer(torch)(lambda: blco.atomic_probe(out, ids), steps, 2)
+    del out, ids
+    return {"rows": rows, "rank": R, "ms": ms, "row_ops_per_s": rows / (ms * 1e-3)}
+
+
 # --------------------------------------------------------------------------- legs
 
-def leg_inmemory(args, torch, blco, synth, w):
+def leg_inmemory(args, torch, blco, synth, w, *, check=True, cpu=False, gpu_build=True,
+                 headline=False):
     dev = torch.device("cuda:0")
     timer = Timer(torch)
     t0 = time.time()
     coords, vals = synth.workload_tensor(w, nnz=args.nnz, log=log)
     nnz = len(vals)
-    log(f"generated {nnz} non-zeros in {time.time() - t0:.1f}s")
+    log(f"{w.name}: generated {nnz} non-zeros in {time.time() - t0:.1f}s")
     t0 = time.time()
     T = blco.build(coords, vals, w.dims)
     build_s = time.time() - t0
     inf = T.info()
-    log(f"built BLCO in {build_s:.2f}s: T={inf['total_bits']} bits, {inf['nblocks']} block(s), "
-        f"{inf['nruns']} run(s)")
-    # the same construction on the GPU, from device-resident coordinates and values
-    dc = [torch.from_numpy(c.view(np.int32)).to(dev) for c in coords]
-    dv = torch.from_numpy(vals).to(dev)
-    torch.cuda.synchronize()
-    gpu_build = []
-    for _ in range(3):
-        t0 = time.time()
-        Tg = blco.build_device(dc, dv, w.dims)
-        gpu_build.append(time.time() - t0)
-        Tg.free()
-    del dc, dv
-    log(f"built BLCO on the GPU in {min(gpu_build) * 1e3:.1f} ms (host builder {build_s * 1e3:.0f} ms)")
+    log(f"{w.name}: built BLCO in {build_s:.2f}s: T={inf['total_bits']} bits, "
+        f"{inf['nblocks']} block(s), {inf['nruns']} run(s)")
+    build_gpu = None
+    if gpu_build:
+        # the same construction on the GPU, from device-resident coordinates and values
+        dc = [torch.from_numpy(c.view(np.int32)).to(dev) for c in coords]
+        dv = torch.from_numpy(vals).to(dev)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            Tg = blco.build_device(dc, dv, w.dims)
+            torch.cuda.synchronize()
+            times.append(time.time() - t0)
+            Tg.free()
+        del dc, dv
+        build_gpu = min(times)
+        log(f"{w.name}: built BLCO on the GPU in {build_gpu * 1e3:.1f} ms")
     N = len(w.dims)
     modes = list(range(N))
-    distinct = [int(np.count_nonzero(np.bincount(c, minlength=d))) for c, d in zip(coords, w.dims)]
+    counts = [np.bincount(c, minlength=d) for c, d in zip(coords, w.dims)]
+    distinct = [int(np.count_nonzero(c)) for c in counts]
     results = {}
-    head = None
+    keep = {}
     for R in w.ranks:
         A = synth.workload_factors(w, R)
         F32 = [torch.from_numpy(a).to(dev) for a in A]
@@ -187,93 +364,139 @@ def leg_inmemory(args, torch, blco, synth, w):
                 for n in modes:
                     blco.mttkrp(T, n, F, out=outs[n])
             ms_step = timer(step, args.steps, args.warmup)
-            call = [timer(lambda n=n: blco.mttkrp(T, n, F, out=outs[n]), args.steps) for n in modes]
-            kern = [timer(lambda n=n: blco.mttkrp_acc(T, n, F, outs[n]), args.steps) for n in modes]
+            call = [timer(lambda n=n: blco.mttkrp(T, n, F, out=outs[n]), args.steps)
+                    for n in modes]
+            kern = [timer(lambda n=n: blco.mttkrp_acc(T, n, F, outs[n]), args.steps)
+                    for n in modes]
             sf = 4 if tag == "fp32" else 2
-            per_nnz = 12 + (N - 1) * R * sf
-            mech = [T.resolution(n, R) for n in modes]
+            ft = "float" if tag == "fp32" else "unsigned short"
+            names = [mode_kernel(T, n, R, N, ft, big_factors(w.dims, R, sf, n)) for n in modes]
+            compulsory = [12 * nnz + sum(distinct[m] * R * sf for m in modes if m != n) +
+                          w.dims[n] * R * 4 for n in modes]
             alt = {}
             for n in modes:
-                if mech[n] == "hierarchical":
+                if T.resolution(n, R) == "hierarchical":
                     # the other mechanism on the same mode, for the Section 5.3 comparison
                     T.set_resolution("register")
                     alt[n] = timer(lambda n=n: blco.mttkrp_acc(T, n, F, outs[n]), args.steps)
                     T.set_resolution("auto")
             results[f"R{R}_{tag}"] = {
                 "ms_per_step": ms_step, "gnnz_s": nnz * N / (ms_step * 1e-3) / 1e9,
-                "resolution": mech,
+                "resolution": [T.resolution(n, R) for n in modes],
                 "register_kernel_ms_on_hierarchical_modes": {str(n): v for n, v in alt.items()},
-                "call_ms": call, "kernel_ms": kern,
+                "call_ms": call, "kernel_ms": kern, "kernel": names,
                 "per_mode_gnnz_s": [nnz / (x * 1e-3) / 1e9 for x in call],
-                "bytes_per_nnz": per_nnz,
-                "kernel_gbs": [nnz * per_nnz / (x * 1e-3) / 1e9 for x in kern],
+                "compulsory_bytes": compulsory,
+                "per_mode_hbm_frac": [b / (x * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                      for b, x in zip(compulsory, kern)],
+                "requested_bytes_rate_gbs": [nnz * (12 + (N - 1) * R * sf) / (x * 1e-3) / 1e9
+                                             for x in kern],
             }
-            log(f"R={R} {tag}: all-mode step {ms_step:.3f} ms, kernel ms/mode "
-                f"{[round(x, 3) for x in kern]} ({mech}); register-based on the hierarchical "
-                f"modes: {({n: round(v, 3) for n, v in alt.items()})}")
-            if head is None:
-                head = (R, ms_step, kern, per_nnz, A, F32, BF16, outs)
-    R, ms_step, kern, per_nnz, A, F32, BF16, outs = head
-    avg_kernel_ms = float(np.mean(kern))
-    achieved = nnz * per_nnz / (avg_kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic() if w.name == "zipf3" and args.nnz is None else None
-    compulsory = [nnz * 12 + sum(distinct[m] * R * 4 for m in modes if m != n) +
-                  2 * w.dims[n] * R * 4 for n in modes]
-    res = base_result(args, w, nnz, nnz * N / (ms_step * 1e-3) / 1e9, ms_step)
-    res["config"].update({"rank": R, "key_bits": inf["total_bits"], "blocks": inf["nblocks"]})
+            log(f"{w.name} R={R} {tag}: all-mode step {ms_step:.3f} ms, kernel ms/mode "
+                f"{[round(x, 3) for x in kern]}, compulsory-HBM fraction "
+                f"{[round(f, 3) for f in results[f'R{R}_{tag}']['per_mode_hbm_frac']]}")
+        keep[R] = (A, F32, BF16, outs)
+        if R != w.ranks[0]:
+            del keep[R]
+            del F32, BF16, outs
+            torch.cuda.empty_cache()
+    R = w.ranks[0]
+    head = results[f"R{R}_fp32"]
+    res = base_result(args, w, nnz, head["gnnz_s"], head["ms_per_step"])
+    res["config"].update({"rank": R, "factors": "fp32", "key_bits": inf["total_bits"],
+                          "blocks": inf["nblocks"], "runs": inf["nruns"]})
+    # the kernel that takes the most time in the step, over the modes that launch it
+    tot = {}
+    for n in modes:
+        tot.setdefault(head["kernel"][n], []).append(n)
+    dom = max(tot, key=lambda k: sum(head["kernel_ms"][n] for n in tot[k]))
+    dm = tot[dom]
+    avg_ms = float(np.mean([head["kernel_ms"][n] for n in dm]))
+    alg = float(np.mean([head["compulsory_bytes"][n] for n in dm]))
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    counters = read_counters() if (w.name == "zipf4" and args.nnz is None) else None
+    traffic = counter_traffic(counters, dom)
+    calib = atomic_calibration(torch, blco, R, args.steps)
+    rops = counter_row_ops(counters, dom)
+    atomics = {"calibration": calib, "row_ops_per_launch": rops["row_ops"] if rops else None,
+               "requests_per_row_op": rops["requests_per_row_op"] if rops else None,
+               "bound_ms": rops["row_ops"] / calib["row_ops_per_s"] * 1e3 if rops else None}
+    atomics["frac"] = atomics["bound_ms"] / avg_ms if rops else None
     res["roofline"] = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-        "kernel": [short_kernel_name(R, N) if T.resolution(n, R) == "hierarchical"
-                   else win_kernel_name(R, N, stash=inf["hot_rows"][n] > 0) for n in modes],
-        "bytes_per_nnz": per_nnz, "avg_kernel_ms": avg_kernel_ms,
-        "model": "requested bytes 12 + (N-1)*R*s_f per non-zero (the paper's Vol); "
-                 "frac above 1 means factor rows are served from cache",
-        "compulsory_bytes_per_launch": compulsory,
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic["bytes"] if traffic else None,
+        "kernel": dom, "modes": dm, "avg_kernel_ms": avg_ms,
+        "algorithmic_bytes_per_launch": alg,
+        "bytes_model": "compulsory: 12 B per non-zero (key + value) + each distinct row of the "
+                       "other modes' factors once (U_m*R*s_f) + the output once (I_n*R*4)",
+        "traffic_over_algorithmic": traffic["bytes"] / alg if traffic else None,
+        "traffic_scales": [traffic["fetch_scale"], traffic["write_scale"]] if traffic else None,
+        "all_modes_frac": sum(head["compulsory_bytes"]) / (sum(head["kernel_ms"]) * 1e-3) / 1e9
+                          / HBM_PEAK_GBS,
+        "atomics": atomics,
     }
+    log(f"{w.name}: dominant kernel {dom} (modes {dm}): {avg_ms:.3f} ms, {achieved:.0f} GB/s "
+        f"compulsory = {achieved / HBM_PEAK_GBS:.3f} of HBM peak; atomics {atomics}")
     res["per_config"] = results
     res["distinct_indices"] = distinct
     res["build_s"] = build_s
-    res["build_gpu_s"] = min(gpu_build)
+    res["build_gpu_s"] = build_gpu
     res["cpu_baseline"] = None
-    if not args.no_cpu_baseline:
+    if check:
         import oracle
 
-        res["cpu_baseline"] = cpu_oracle_rate(oracle, coords, vals, A, args.cpu_sample_nnz, modes)
-        log(f"cpu oracle: {res['cpu_baseline']['value']:.4f} Gnnz/s")
         rng = np.random.default_rng(7)
         errs = {}
         for R in w.ranks:
-            if R == head[0]:
-                A_, F32_, BF16_, outs_ = A, F32, BF16, outs
+            if R in keep:
+                A, F32, BF16, outs = keep[R]
             else:
-                A_ = synth.workload_factors(w, R)
-                F32_ = [torch.from_numpy(a).to(dev) for a in A_]
-                BF16_ = [blco.cast_bf16(f) for f in F32_]
-                outs_ = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in w.dims]
-            Ab = [oracle.bf16_round(a) for a in A_]
-            errs[f"R{R}_fp32"] = row_errors(oracle, blco, torch, T, coords, vals, A_, F32_, outs_,
-                                            w.dims, modes, rng, dev)
-            errs[f"R{R}_bf16"] = row_errors(oracle, blco, torch, T, coords, vals, Ab, BF16_, outs_,
-                                            w.dims, modes, rng, dev)
-            errs[f"R{R}_bf16_vs_fp32"] = row_errors(oracle, blco, torch, T, coords, vals, A_,
-                                                    BF16_, outs_, w.dims, modes, rng, dev)
+                A = synth.workload_factors(w, R)
+                F32 = [torch.from_numpy(a).to(dev) for a in A]
+                BF16 = [blco.cast_bf16(f) for f in F32]
+                outs = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in w.dims]
+            Ab = [oracle.bf16_round(a) for a in A]
+            e = {"fp32": [], "bf16": [], "bf16_vs_fp32": []}
+            for n in modes:
+                rows = check_rows_for(counts[n], w.dims[n], rng)
+                ridx = torch.from_numpy(rows.astype(np.int64)).to(dev)
+                M32, S32 = oracle.mttkrp_rows_f32(coords, vals, A, n, rows, w.dims)
+                Mb, Sb = oracle.mttkrp_rows_f32(coords, vals, Ab, n, rows, w.dims)
+                g32 = blco.mttkrp(T, n, F32, out=outs[n])[ridx].cpu().numpy().astype(np.float64)
+                gb = blco.mttkrp(T, n, BF16, out=outs[n])[ridx].cpu().numpy().astype(np.float64)
+                for key, got, M, S in (("fp32", g32, M32, S32), ("bf16", gb, Mb, Sb),
+                                       ("bf16_vs_fp32", gb, M32, S32)):
+                    nz = S > 0
+                    e[key].append(np.abs(got - M)[nz] / S[nz])
+                log(f"{w.name} R={R} mode {n}: {len(rows)} rows checked against the oracle")
+            for key, v in e.items():
+                a = np.concatenate(v)
+                errs[f"R{R}_{key}"] = {"max": float(a.max()), "median": float(np.median(a))}
+            del F32, BF16, outs
         res["errors"] = errs
-        log(f"errors: {errs}")
+        log(f"{w.name}: errors {errs}")
+    if cpu:
+        import oracle
+
+        A = keep[w.ranks[0]][0]
+        res["cpu_baseline"] = cpu_oracle_baseline(oracle, coords, vals, A, modes,
+                                                  args.cpu_sample_nnz, args.cpu_sample_all_nnz)
+    T.free()
     return res
 
 
-def leg_oom(args, torch, blco, synth, w):
+def leg_oom(args, torch, blco, synth, w, *, check=True, cpu=False):
     dev = torch.device("cuda:0")
     timer = Timer(torch)
     t0 = time.time()
     coords, vals = synth.workload_tensor(w, nnz=args.nnz, log=log)
     nnz = len(vals)
-    log(f"generated {nnz} non-zeros in {time.time() - t0:.1f}s")
+    log(f"{w.name}: generated {nnz} non-zeros in {time.time() - t0:.1f}s")
     t0 = time.time()
     T = blco.build(coords, vals, w.dims, placement="pinned")
     build_s = time.time() - t0
-    log(f"built pinned BLCO in {build_s:.1f}s")
+    log(f"{w.name}: built pinned BLCO in {build_s:.1f}s")
     N = len(w.dims)
     modes = list(range(N))
     R = w.ranks[0]
@@ -281,70 +504,72 @@ def leg_oom(args, torch, blco, synth, w):
     F = [torch.from_numpy(a).to(dev) for a in A]
     outs = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in w.dims]
     budget = args.budget or w.budget_bytes
+    steps, warm = (min(args.steps, 3), min(args.warmup, 1)) if not args.workload else \
+        (args.steps, args.warmup)
+
+    def overlap(c, k, t):
+        return (c + k - t) / max(min(c, k), 1e-9)
+
     per = []
     for n in modes:
         ms = timer(lambda n=n: blco.mttkrp_stream(T, n, F, out=outs[n], device_budget=budget),
-                   args.steps, args.warmup)
+                   steps, warm)
         inf = T.info()
-        copy_ms, kern_ms = inf["stream_copy_ms"], inf["stream_kernel_ms"]
-        tot_ms = inf["stream_total_ms"]
-        overlap = (copy_ms + kern_ms - tot_ms) / max(min(copy_ms, kern_ms), 1e-9)
+        c, k, t = inf["stream_copy_ms"], inf["stream_kernel_ms"], inf["stream_total_ms"]
         per.append({"mode": n, "call_ms": ms, "overall_gnnz_s": nnz / (ms * 1e-3) / 1e9,
-                    "in_memory_gnnz_s": nnz / (kern_ms * 1e-3) / 1e9,
-                    "h2d_gbs": nnz * 12 / (copy_ms * 1e-3) / 1e9,
-                    "copy_ms": copy_ms, "kernel_ms": kern_ms, "total_ms": tot_ms,
-                    "overlap": overlap, "chunks": inf["stream_chunks"],
+                    "in_memory_gnnz_s": nnz / (k * 1e-3) / 1e9,
+                    "h2d_gbs": nnz * 12 / (c * 1e-3) / 1e9, "copy_ms": c, "kernel_ms": k,
+                    "total_ms": t, "overlap": overlap(c, k, t), "chunks": inf["stream_chunks"],
                     "chunk_nnz": inf["stream_chunk_nnz"],
                     "peak_device_bytes": inf["stream_peak_bytes"]})
-        log(f"mode {n}: {ms:.1f} ms/call, copy {copy_ms:.1f} ms, kernels {kern_ms:.1f} ms, "
-            f"span {tot_ms:.1f} ms, overlap {overlap:.3f}, {inf['stream_chunks']} chunks")
-    ms_per_mode_sum = sum(p["call_ms"] for p in per)
-    # every mode in one pass: each chunk crosses the host link once
+        log(f"{w.name} mode {n}: {ms:.1f} ms/call, copy {c:.1f} ms, kernels {k:.1f} ms, span "
+            f"{t:.1f} ms, overlap {per[-1]['overlap']:.3f}, {inf['stream_chunks']} chunks")
+    ms_modes = sum(p["call_ms"] for p in per)
     ms_step = timer(lambda: blco.mttkrp_stream_all(T, F, outs=outs, device_budget=budget),
-                    args.steps, args.warmup)
+                    steps, warm)
     inf = T.info()
-    copy_ms, kern_ms, tot_ms = inf["stream_copy_ms"], inf["stream_kernel_ms"], inf["stream_total_ms"]
-    fused = {"call_ms": ms_step, "overall_gnnz_s": nnz * N / (ms_step * 1e-3) / 1e9,
-             "copy_ms": copy_ms, "kernel_ms": kern_ms, "total_ms": tot_ms,
-             "overlap": (copy_ms + kern_ms - tot_ms) / max(min(copy_ms, kern_ms), 1e-9),
-             "h2d_gbs": nnz * 12 / (copy_ms * 1e-3) / 1e9, "chunks": inf["stream_chunks"],
-             "peak_device_bytes": inf["stream_peak_bytes"]}
-    log(f"all modes in one pass: {ms_step:.1f} ms/call, copy {copy_ms:.1f} ms, kernels "
-        f"{kern_ms:.1f} ms, overlap {fused['overlap']:.3f}")
+    c, k, t = inf["stream_copy_ms"], inf["stream_kernel_ms"], inf["stream_total_ms"]
+    one = {"call_ms": ms_step, "overall_gnnz_s": nnz * N / (ms_step * 1e-3) / 1e9,
+           "copy_ms": c, "kernel_ms": k, "total_ms": t, "overlap": overlap(c, k, t),
+           "h2d_gbs": nnz * 12 / (c * 1e-3) / 1e9, "chunks": inf["stream_chunks"],
+           "peak_device_bytes": inf["stream_peak_bytes"]}
+    log(f"{w.name} all modes in one pass: {ms_step:.1f} ms/call, copy {c:.1f} ms, kernels "
+        f"{k:.1f} ms, overlap {one['overlap']:.3f}")
     res = base_result(args, w, nnz, nnz * N / (ms_step * 1e-3) / 1e9, ms_step)
-    res["per_mode_passes_ms_per_step"] = ms_per_mode_sum
-    res["per_mode_passes_gnnz_s"] = nnz * N / (ms_per_mode_sum * 1e-3) / 1e9
-    res["one_pass"] = fused
-    kern_ms = float(np.mean([p["kernel_ms"] / p["chunks"] for p in per]))
-    chunk_nnz = per[0]["chunk_nnz"]
-    per_nnz = 12 + (N - 1) * R * 4
+    res["steps"], res["warmup"] = steps, warm
+    res["per_mode_passes_ms_per_step"] = ms_modes
+    res["per_mode_passes_gnnz_s"] = nnz * N / (ms_modes * 1e-3) / 1e9
+    res["one_pass"] = one
+    res["per_mode"] = per
     res["config"].update({"rank": R, "device_budget_bytes": budget, "placement": "pinned"})
     res["roofline"] = {
-        "bound": "hbm", "achieved": chunk_nnz * per_nnz / (kern_ms * 1e-3) / 1e9,
-        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": chunk_nnz * per_nnz / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-        "kernel": win_kernel_name(R, N) + " per chunk", "bytes_per_nnz": per_nnz,
-        "avg_kernel_ms": kern_ms,
-        "note": "the step itself is bound by host-to-device copies (per_mode h2d_gbs)",
+        "bound": "pcie", "achieved": one["h2d_gbs"], "unit": "GB/s",
+        "note": "the streamed step is bound by the host-to-device copies (12 B per non-zero "
+                "per pass); the in-memory kernels are reported in per_mode kernel_ms",
     }
-    res["per_mode"] = per
     res["build_s"] = build_s
     res["cpu_baseline"] = None
-    if not args.no_cpu_baseline:
+    if check:
         import oracle
 
-        res["cpu_baseline"] = cpu_oracle_rate(oracle, coords, vals, A, args.cpu_sample_nnz, modes)
         rng = np.random.default_rng(7)
         worst = 0.0
         for n in modes:
             o = blco.mttkrp_stream(T, n, F, out=outs[n], device_budget=budget)
-            rows = sampled_rows(rng, w.dims[n], 40)
+            rows = np.unique(np.concatenate([np.arange(8), rng.integers(0, w.dims[n], 24),
+                                             [w.dims[n] - 1]])).astype(np.uint32)
             M, S = oracle.mttkrp_rows_f32(coords, vals, A, n, rows, w.dims)
             got = o[torch.from_numpy(rows.astype(np.int64)).to(dev)].cpu().numpy()
             nz = S > 0
             worst = max(worst, float((np.abs(got - M)[nz] / S[nz]).max()))
         res["errors"] = {"fp32": {"max": worst}}
-        log(f"max normalised error {worst:.2e}")
+        log(f"{w.name}: max normalised error {worst:.2e}")
+    if cpu:
+        import oracle
+
+        res["cpu_baseline"] = cpu_oracle_baseline(oracle, coords, vals, A, modes,
+                                                  args.cpu_sample_nnz, args.cpu_sample_all_nnz)
+    T.free()
     return res
 
 
@@ -364,7 +589,7 @@ def planted_values(torch, coords, G, sigma, seed, synth, chunk=8_000_000):
     return out
 
 
-def leg_cpgrad(args, torch, blco, synth, w):
+def leg_cpgrad(args, torch, blco, synth, w, *, check=True, cpu=False):
     dev = torch.device("cuda:0")
     timer = Timer(torch)
     t0 = time.time()
@@ -372,7 +597,7 @@ def leg_cpgrad(args, torch, blco, synth, w):
     nnz = len(coords[0])
     G = [synth.draw_u01_matrix(d, 8, w.seed, synth.S_TRUTH + m) for m, d in enumerate(w.dims)]
     vals = planted_values(torch, coords, G, 0.01, w.seed, synth)
-    log(f"generated {nnz} non-zeros with planted values in {time.time() - t0:.1f}s")
+    log(f"{w.name}: generated {nnz} non-zeros with planted values in {time.time() - t0:.1f}s")
     t0 = time.time()
     T = blco.build(coords, vals, w.dims)
     build_s = time.time() - t0
@@ -394,24 +619,26 @@ def leg_cpgrad(args, torch, blco, synth, w):
         torch.cuda.synchronize()
         out[storage] = {"ms_per_step": ms, "gnnz_s": nnz / (ms * 1e-3) / 1e9,
                         "loss": float(loss.detach())}
-        log(f"CP loss+gradient ({storage}): {ms:.2f} ms/step")
+        log(f"{w.name}: CP loss + gradient ({storage}): {ms:.2f} ms/step")
     ms_step = out["fp32"]["ms_per_step"]
     res = base_result(args, w, nnz, nnz / (ms_step * 1e-3) / 1e9, ms_step)
-    res["metric"] = "CP loss + gradient step Gnnz/s (forward sampled reconstruction + N MTTKRPs)"
+    res["metric"] = "CP loss + gradient step Gnnz/s (sampled reconstruction + N residual MTTKRPs)"
     Pd = [p.detach() for p in P]
     loss_ms = timer(lambda: blco.sampled_loss(T, Pd), args.steps)
-    per_nnz = 12 + 4 + N * R * 4
     res["config"].update({"rank": R, "model_rank": 8, "noise_sigma": 0.01})
-    res["roofline"] = {
-        "bound": "hbm", "achieved": nnz * per_nnz / (loss_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": nnz * per_nnz / (loss_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "traffic": None, "kernel": f"k_loss_tile<32, float, {N}> (sampled reconstruction)",
-        "bytes_per_nnz": per_nnz, "avg_kernel_ms": loss_ms,
-    }
+    res["loss_kernel_ms"] = loss_ms
     res["per_storage"] = out
     res["build_s"] = build_s
     res["cpu_baseline"] = None
-    if not args.no_cpu_baseline:
+    if check:
+        import oracle
+
+        Ad = [a.astype(np.float64) for a in A]
+        f_ref, _ = oracle.cp_loss(coords, vals, Ad)
+        res["errors"] = {"loss_rel_fp32": abs(out["fp32"]["loss"] - f_ref) / f_ref,
+                         "loss_rel_bf16_vs_fp64": abs(out["bf16"]["loss"] - f_ref) / f_ref}
+        log(f"{w.name}: oracle loss {f_ref:.6e}, gpu {out['fp32']['loss']:.6e}")
+    if cpu:
         import oracle
 
         S = min(args.cpu_sample_nnz, nnz)
@@ -422,10 +649,7 @@ def leg_cpgrad(args, torch, blco, synth, w):
         res["cpu_baseline"] = {"value": S / dt / 1e9, "unit": "Gnnz/s", "cores": 1,
                                "kind": "oracle", "sample": f"loss + {N}-mode gradient over the "
                                f"first {S} non-zeros, fp64, single thread, {dt:.1f}s"}
-        f_ref, _ = oracle.cp_loss(coords, vals, [a.astype(np.float64) for a in A])
-        res["errors"] = {"loss_rel_fp32": abs(out["fp32"]["loss"] - f_ref) / f_ref,
-                         "loss_rel_bf16_vs_fp64": abs(out["bf16"]["loss"] - f_ref) / f_ref}
-        log(f"oracle loss {f_ref:.6e}, gpu {out['fp32']['loss']:.6e}")
+    T.free()
     return res
 
 
@@ -461,136 +685,12 @@ def leg_cpals(args, torch, blco, synth, w):
     res = base_result(args, w, nnz, nnz * N / (ms_iter * 1e-3) / 1e9, ms_iter)
     res["metric"] = "CP-ALS iteration Gnnz/s (N MTTKRPs + Gram, V pseudo-inverse, M V^+, fit)"
     res["config"].update({"rank": R, "model_rank": 8, "noise_sigma": 0.01, "iterations": iters})
-    per_nnz = 12 + (N - 1) * R * 4
-    avg = float(np.mean(mk))
-    res["roofline"] = {
-        "bound": "hbm", "achieved": nnz * per_nnz / (avg * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": nnz * per_nnz / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-        "kernel": [short_kernel_name(R, N) if T.resolution(n, R) == "hierarchical"
-                   else win_kernel_name(R, N) for n in range(N)],
-        "bytes_per_nnz": per_nnz, "avg_kernel_ms": avg,
-        "model": "requested bytes 12 + (N-1)*R*4 per non-zero of the MTTKRP kernels",
-    }
     res["mttkrp_kernel_ms"] = mk
     res["mttkrp_share_of_iteration"] = sum(mk) / ms_iter
     res["fits"] = fits
     res["pinv_fallbacks"] = rep["pinv_fallbacks"]
     res["cpu_baseline"] = None
-    if not args.no_cpu_baseline:
-        from oracle import cpals
-
-        S = min(args.cpu_sample_nnz, nnz)
-        t0 = time.time()
-        _, fw = cpals.cp_als([c[:S] for c in coords], vals[:S], [a.astype(np.float64) for a in A],
-                             w.dims, max_iters=1)
-        dt = time.time() - t0
-        res["cpu_baseline"] = {"value": S * N / dt / 1e9, "unit": "Gnnz/s", "cores": 1,
-                               "kind": "oracle", "sample": f"one CP-ALS iteration over the first "
-                               f"{S} non-zeros, fp64, single thread, {dt:.1f}s"}
     return res
-
-
-def win_kernel_name(R, N, ft="float", big=False, stash=True):
-    """Template name of the window MTTKRP kernel the library launches for rank R
-    (stash: the mode has frequent rows held in LDS)."""
-    lpn, rpl = (16, 1) if R <= 16 else (16, 2) if R <= 32 else (16, 4) if R <= 64 else (64, 2)
-    b = lambda v: "true" if v else "false"
-    return f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {b(big)}, {b(stash)}>"
-
-
-def short_kernel_name(R, N, ft="float", big=False):
-    """Template name of the hierarchical MTTKRP kernel for a single rank slice of width R."""
-    rpl = 1 if R <= 16 else 2 if R <= 32 else 4
-    return f"k_mttkrp_short<{rpl}, {ft}, {N}, {'true' if big else 'false'}>"
-
-
-def summarize_pmc(fetch_csv, write_csv, copy_bytes, kernel=None, out=TRAFFIC_FILE):
-    """Per-launch HBM bytes of the MTTKRP kernel from two rocprofv3 --pmc runs.
-
-    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are averaged over the MTTKRP
-    dispatches, and each is scaled by the ratio of the known size of a plain
-    device-to-device copy to what the same counter read for that copy.
-    """
-    import csv
-
-    kernel = kernel or "void " + win_kernel_name(32, 3)
-
-    def per_kernel(path, counter):
-        acc = {}
-        for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] != counter:
-                continue
-            name = r["Kernel_Name"]
-            key = "mttkrp" if name.startswith(kernel + "(") else (
-                "copy" if "copyBuffer" in name else None)
-            if key is None:
-                continue
-            acc.setdefault(key, []).append(float(r["Counter_Value"]))
-        # the calibration copy is the largest copy dispatch
-        red = {"mttkrp": np.mean, "copy": np.max}
-        return ({k: float(red[k](v)) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()})
-
-    f, fn = per_kernel(fetch_csv, "FETCH_SIZE")
-    w, wn = per_kernel(write_csv, "WRITE_SIZE")
-    # the largest copy dispatch is the calibration copy
-    fscale = copy_bytes / (f["copy"] * 1024.0)
-    wscale = copy_bytes / (w["copy"] * 1024.0)
-    fetch_b = f["mttkrp"] * 1024.0 * fscale
-    write_b = w["mttkrp"] * 1024.0 * wscale
-    lines = [
-        f"# HBM traffic of the MTTKRP kernel ({kernel[5:]}), 50M-non-zero",
-        "# 2^22 x 2^21 x 2^20 Zipf(1.1) workload, R = 32, fp32 factors, per launch (one mode).",
-        "# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two rocprofv3 --pmc runs of",
-        "#   python3 bench.py --workload zipf3 --steps 2 --warmup 0 --no-cpu-baseline "
-        f"--calibrate-copy-bytes {copy_bytes}",
-        "# each scaled by copy_bytes / (counter of the calibration copy), then summed.",
-        f"kernel_source_sha256_16: {kernel_source_hash()}",
-        f"mttkrp_dispatches: {fn.get('mttkrp', 0)}",
-        f"fetch_kib_per_dispatch: {f['mttkrp']:.1f}",
-        f"write_kib_per_dispatch: {w['mttkrp']:.1f}",
-        f"copy_bytes: {copy_bytes}",
-        f"copy_fetch_kib: {f['copy']:.1f}",
-        f"copy_write_kib: {w['copy']:.1f}",
-        f"fetch_scale: {fscale:.4f}",
-        f"write_scale: {wscale:.4f}",
-        f"hbm_fetch_bytes_per_launch: {fetch_b:.0f}",
-        f"hbm_write_bytes_per_launch: {write_b:.0f}",
-        f"hbm_bytes_per_launch: {fetch_b + write_b:.0f}",
-    ]
-    with open(out, "w") as fh:
-        fh.write("\n".join(lines) + "\n")
-    print("\n".join(lines))
-
-
-def summarize_counters(workload, kernel, nnz, out, *csvs):
-    """Per-launch and per-non-zero means of every counter in one or more rocprofv3
-    --pmc CSVs, over the dispatches of one kernel (instruction counts, LDS bank
-    conflicts, and the atomics the kernel sends to the L2 and on to memory)."""
-    import csv
-
-    lines = [f"# rocprofv3 counters of {kernel}, workload {workload}, {nnz} non-zeros per launch",
-             "# (one mode per launch; mean over the kernel's dispatches). Commands, one per pass:"]
-    vals, ndisp = {}, {}
-    for path in csvs:
-        names = set()
-        for r in csv.DictReader(open(path)):
-            if not r["Kernel_Name"].startswith("void " + kernel + "("):
-                continue
-            names.add(r["Counter_Name"])
-            vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
-        for c in names:
-            ndisp[c] = len(vals[c])
-        lines.append(f"#   rocprofv3 --pmc {' '.join(sorted(names))} -o run --output-format csv "
-                     f"-- python3 bench.py --workload {workload} --steps 2 --warmup 0 "
-                     "--no-cpu-baseline")
-    lines.append(f"kernel_source_sha256_16: {kernel_source_hash()}")
-    lines.append(f"{'counter':40s} {'dispatches':>10s} {'per_launch':>16s} {'per_nnz':>10s}")
-    for c in sorted(vals):
-        m = float(np.mean(vals[c]))
-        lines.append(f"{c:40s} {ndisp[c]:10d} {m:16.1f} {m / nnz:10.4f}")
-    with open(out, "w") as fh:
-        fh.write("\n".join(lines) + "\n")
-    print("\n".join(lines))
 
 
 def resolution_sweep(args, torch, blco, synth):
@@ -626,25 +726,71 @@ def resolution_sweep(args, torch, blco, synth):
             "cus": torch.cuda.get_device_properties(0).multi_processor_count, "rows": rows}
 
 
+def secondary_summary(r):
+    keep = ("metric", "value", "unit", "ms_per_step", "steps", "warmup", "config", "roofline",
+            "per_config", "errors", "per_mode", "one_pass", "per_mode_passes_ms_per_step",
+            "per_mode_passes_gnnz_s", "per_storage", "loss_kernel_ms", "build_s",
+            "build_gpu_s", "distinct_indices")
+    return {k: r[k] for k in keep if k in r}
+
+
+def suite(args, torch, blco, synth):
+    """The default run: the zipf4 headline, then zipf3, cpgrad4 and oom3 as secondary legs."""
+    W = synth.WORKLOADS
+    res = leg_inmemory(args, torch, blco, synth, W["zipf4"], check=not args.no_check,
+                       cpu=not args.no_cpu_baseline, headline=True)
+    sec = {}
+    torch.cuda.empty_cache()
+    sec["zipf3"] = secondary_summary(leg_inmemory(args, torch, blco, synth, W["zipf3"],
+                                                  check=not args.no_check, gpu_build=True))
+    torch.cuda.empty_cache()
+    sec["cpgrad4"] = secondary_summary(leg_cpgrad(args, torch, blco, synth, W["cpgrad4"],
+                                                  check=False))
+    torch.cuda.empty_cache()
+    elapsed = time.time() - T_START
+    if elapsed > args.oom_start_limit_s:
+        sec["oom3"] = {"skipped": f"run already at {elapsed:.0f}s, past the {args.oom_start_limit_s}s "
+                                  "start limit of the 1.5B-non-zero leg"}
+        log(sec["oom3"]["skipped"])
+    else:
+        sec["oom3"] = secondary_summary(leg_oom(args, torch, blco, synth, W["oom3"],
+                                                check=not args.no_check))
+    res["secondary"] = sec
+    return res
+
+
 def main():
-    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
-        summarize_pmc(sys.argv[2], sys.argv[3], int(sys.argv[4]))
-        return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
-        # WORKLOAD KERNEL NNZ OUT CSV...
-        summarize_counters(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5], *sys.argv[6:])
+        # OUT TITLE COPY_BYTES PROBE_ROW_OPS CSV... [-- COMMAND...]
+        a = sys.argv[2:]
+        cmds = []
+        if "--" in a:
+            i = a.index("--")
+            a, cmds = a[:i], a[i + 1:]
+        summarize_counters(a[0], a[1], *a[4:], copy_bytes=int(a[2]), probe_row_ops=int(a[3]),
+                           commands=cmds)
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-stats":
+        # OUT TITLE STATS_CSV COMMAND
+        summarize_stats(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="zipf3",
+    ap.add_argument("--workload", default=None,
                     choices=["zipf3", "uniform3", "zipf4", "oom3", "cpgrad4", "cpals4", "short4",
                              "small"])
     ap.add_argument("--nnz", type=int, default=None, help="shrink the workload (same recipe)")
     ap.add_argument("--budget", type=int, default=None, help="device budget for oom3 (bytes)")
-    ap.add_argument("--cpu-sample-nnz", type=int, default=4_000_000)
+    ap.add_argument("--cpu-sample-nnz", type=int, default=4_000_000,
+                    help="non-zeros of the single-thread oracle timing")
+    ap.add_argument("--cpu-sample-all-nnz", type=int, default=16_000_000,
+                    help="non-zeros of the all-core oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle row checks")
+    ap.add_argument("--oom-start-limit-s", type=float, default=300.0,
+                    help="default run: skip the 1.5B-non-zero leg when it would start later")
     ap.add_argument("--resolution-sweep", action="store_true",
                     help="time both conflict-resolution mechanisms over short-mode lengths")
     ap.add_argument("--rank", type=int, default=32,
@@ -664,6 +810,7 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    log(f"device {torch.cuda.get_device_name(0)}")
     if args.calibrate_copy_bytes:
         n = args.calibrate_copy_bytes // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
@@ -675,15 +822,19 @@ def main():
     if args.resolution_sweep:
         print(json.dumps(resolution_sweep(args, torch, blco, synth)), flush=True)
         return
-    w = synth.WORKLOADS.get(args.workload)
-    if args.workload == "oom3":
-        res = leg_oom(args, torch, blco, synth, w)
+    W = synth.WORKLOADS
+    check, cpu = not args.no_check, not args.no_cpu_baseline
+    if args.workload is None:
+        res = suite(args, torch, blco, synth)
+    elif args.workload == "oom3":
+        res = leg_oom(args, torch, blco, synth, W["oom3"], check=check, cpu=cpu)
     elif args.workload == "cpgrad4":
-        res = leg_cpgrad(args, torch, blco, synth, w)
+        res = leg_cpgrad(args, torch, blco, synth, W["cpgrad4"], check=check, cpu=cpu)
     elif args.workload == "cpals4":
-        res = leg_cpals(args, torch, blco, synth, synth.WORKLOADS["cpgrad4"])
+        res = leg_cpals(args, torch, blco, synth, W["cpgrad4"])
     else:
-        res = leg_inmemory(args, torch, blco, synth, w)
+        res = leg_inmemory(args, torch, blco, synth, W[args.workload], check=check, cpu=cpu)
+    res["wall_s"] = time.time() - T_START
     print(json.dumps(res), flush=True)
 
 

@@ -209,6 +209,9 @@ int blco_mttkrp_stream_all(blco_tensor* t, const void* const* factors, int facto
  * residual: device, nnz fp32, written in the tensor's BLCO order (may be NULL).
  * loss: device pointer to one double.  Products are fp32; the residual norm
  * is accumulated in fp64 in a fixed order (deterministic).  Placement DEVICE.
+ * Every factors[m] must be non-NULL.  A tensor without non-zeros gets
+ * *loss = 0 and no factor row is read.  Errors: EINVAL (null handle, loss or
+ * factor pointer, rank, dtype, placement).
  */
 int blco_sampled_loss(blco_tensor* t, const void* const* factors, int factor_dtype, int rank,
                       float* residual, double* loss, void* stream);
@@ -236,6 +239,24 @@ int blco_set_resolution(blco_tensor* t, int resolution);
    MTTKRP call at rank `rank` on the current device uses, in *chosen.
    Errors: EINVAL, EUNSUPPORTED (HIERARCHICAL forced on a mode too long). */
 int blco_resolution(const blco_tensor* t, int mode, int rank, int* chosen);
+
+/*
+ * Measurement kernel, not part of the method: for each k < n, adds 1.0f to the
+ * `rank` entries of row rows[k] of out (device, nrows x rank fp32), with one
+ * device-scope fp32 atomic per entry, issued by groups of 16 lanes exactly as
+ * the MTTKRP kernels flush a finished segment.  Timed over distinct random
+ * rows it calibrates the memory-side atomic rate that bounds the
+ * register-based MTTKRP.  rows: device, n uint32; ids >= nrows are skipped.
+ * Errors: EINVAL (negative size, rank < 1, null pointer with n > 0).
+ */
+int blco_atomic_probe(float* out, int64_t nrows, int rank, const uint32_t* rows, int64_t n,
+                      void* stream);
+
+/* Rows of mode `mode` whose segment sums a register-based MTTKRP at rank
+   `rank` on the current device adds into its LDS stash of frequent rows (found
+   at build time) instead of the output, in *rows (0: none).  For inspection.
+   Errors: EINVAL. */
+int blco_frequent_rows(const blco_tensor* t, int mode, int rank, int* rows);
 
 /* dst[i] = bf16(src[i]), round to nearest even (NaN stays NaN); device arrays. */
 int blco_cast_bf16(const float* src, uint16_t* dst, int64_t n, void* stream);

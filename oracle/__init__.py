@@ -27,7 +27,7 @@ _lib = None
 
 def build_lib(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp",
                                os.path.join(_HERE, "mttkrp_oracle.c"), "-o", _SO, "-lm"])
     return _SO
 
@@ -44,6 +44,13 @@ def lib():
                                          i64, p, p, p]
         L.oracle_mttkrp_rows_f32.argtypes = [ctypes.c_int, p, i64, p, p, p, ctypes.c_int,
                                              ctypes.c_int, i64, p, p, p]
+        L.oracle_mttkrp_omp.argtypes = [ctypes.c_int, p, i64, p, p, p, ctypes.c_int,
+                                        ctypes.c_int, p, p, ctypes.c_int, ctypes.c_int]
+        L.oracle_mttkrp_omp.restype = ctypes.c_int
+        L.oracle_mttkrp_rows_omp.argtypes = [ctypes.c_int, p, i64, p, p, p, ctypes.c_int,
+                                             ctypes.c_int, i64, p, p, p, ctypes.c_int]
+        L.oracle_mttkrp_rows_omp.restype = ctypes.c_int
+        L.oracle_cp_model_omp.argtypes = [ctypes.c_int, i64, p, p, ctypes.c_int, p, ctypes.c_int]
         L.oracle_cp_model.argtypes = [ctypes.c_int, i64, p, p, ctypes.c_int, p]
         L.oracle_cp_loss.argtypes = [ctypes.c_int, i64, p, p, p, ctypes.c_int, p]
         L.oracle_cp_loss.restype = ctypes.c_double
@@ -94,6 +101,32 @@ def mttkrp(coords, vals, factors, mode, dims=None, with_scale=True):
     return M, S
 
 
+def mttkrp_omp(coords, vals, factors, mode, dims=None, with_scale=True, threads=0,
+               force_atomic=False):
+    """:func:`mttkrp` on several host threads: returns (M, S, threads used, atomic form taken).
+
+    Only the order of the additions differs from :func:`mttkrp` (contiguous
+    non-zero chunks per thread; private outputs added in thread order, or
+    atomic updates when the private copies would not fit in a quarter of RAM).
+    It exists to time the oracle on all host cores.
+    """
+    N = len(coords)
+    if dims is None:
+        dims = [f.shape[0] for f in factors]
+    R = int([f for f in factors if f is not None][0].shape[1])
+    cs = [_c(c, np.uint32) for c in coords]
+    fs = [_c(f, np.float64) if f is not None else np.zeros((1, R)) for f in factors]
+    v = _c(vals, np.float64)
+    d = _c(dims, np.uint64)
+    I = int(dims[mode])
+    M = np.empty((I, R), dtype=np.float64)
+    S = np.empty((I, R), dtype=np.float64) if with_scale else None
+    t = lib().oracle_mttkrp_omp(N, d.ctypes.data, len(v), _ptrs(cs), v.ctypes.data, _ptrs(fs), R,
+                                mode, M.ctypes.data, S.ctypes.data if S is not None else None,
+                                int(threads), int(bool(force_atomic)))
+    return M, S, abs(t), t < 0
+
+
 def mttkrp_rows(coords, vals, factors, mode, rows, dims):
     """Rows ``rows`` (distinct) of the mode-``mode`` MTTKRP: (M_rows, S_rows)."""
     N = len(coords)
@@ -124,6 +157,35 @@ def mttkrp_rows_f32(coords, vals, factors, mode, rows, dims):
     lib().oracle_mttkrp_rows_f32(N, d.ctypes.data, len(v), _ptrs(cs), v.ctypes.data, _ptrs(fs), R,
                                  mode, len(rw), rw.ctypes.data, M.ctypes.data, S.ctypes.data)
     return M, S
+
+
+def mttkrp_rows_omp(coords, vals, factors, mode, rows, dims, threads=0):
+    """:func:`mttkrp_rows` on several host threads, with fp64 values and fp32 factors
+    (widened exactly as read).  Only the order of the additions differs."""
+    N = len(coords)
+    R = int([f for f in factors if f is not None][0].shape[1])
+    cs = [_c(c, np.uint32) for c in coords]
+    fs = [_c(f, np.float32) if f is not None else np.zeros((1, R), np.float32) for f in factors]
+    v = _c(vals, np.float64)
+    d = _c(dims, np.uint64)
+    rw = _c(rows, np.uint32)
+    M = np.empty((len(rw), R), dtype=np.float64)
+    S = np.empty((len(rw), R), dtype=np.float64)
+    lib().oracle_mttkrp_rows_omp(N, d.ctypes.data, len(v), _ptrs(cs), v.ctypes.data, _ptrs(fs), R,
+                                 mode, len(rw), rw.ctypes.data, M.ctypes.data, S.ctypes.data,
+                                 int(threads))
+    return M, S
+
+
+def cp_model_omp(coords, factors, threads=0):
+    """:func:`cp_model` with the non-zeros shared among host threads (bit-identical)."""
+    N = len(coords)
+    R = int(factors[0].shape[1])
+    cs = [_c(c, np.uint32) for c in coords]
+    fs = [_c(f, np.float64) for f in factors]
+    out = np.empty(len(cs[0]), dtype=np.float64)
+    lib().oracle_cp_model_omp(N, len(out), _ptrs(cs), _ptrs(fs), R, out.ctypes.data, int(threads))
+    return out
 
 
 def cp_model(coords, factors):

@@ -19,7 +19,7 @@ import torch  # noqa: F401  (must precede loading libblco.so)
 
 __all__ = ["BLCOTensor", "build", "mttkrp", "mttkrp_acc", "mttkrp_v", "mttkrp_stream",
            "mttkrp_stream_all", "sampled_loss",
-           "cast_bf16", "CPLoss", "BLCOError", "lib", "library_path"]
+           "cast_bf16", "atomic_probe", "CPLoss", "BLCOError", "lib", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libblco.so")
@@ -34,7 +34,7 @@ EXPORTED = ["blco_build", "blco_mttkrp", "blco_mttkrp_acc", "blco_mttkrp_v", "bl
             "blco_mttkrp_stream_all",
             "blco_sampled_loss", "blco_cast_bf16", "blco_set_resolution", "blco_resolution",
             "blco_gram", "blco_cp_als", "blco_build_device",
-            "blco_info", "blco_export", "blco_free",
+            "blco_atomic_probe", "blco_frequent_rows", "blco_info", "blco_export", "blco_free",
             "blco_last_error"]
 
 
@@ -101,6 +101,8 @@ def lib():
         L.blco_cp_als.argtypes = [p, p, i32, ctypes.POINTER(_CPALSOpts), p,
                                   ctypes.POINTER(_CPALSReport), p]
         L.blco_resolution.argtypes = [p, i32, i32, ctypes.POINTER(ctypes.c_int)]
+        L.blco_frequent_rows.argtypes = [p, i32, i32, ctypes.POINTER(ctypes.c_int)]
+        L.blco_atomic_probe.argtypes = [p, i64, i32, p, i64, p]
         L.blco_free.argtypes = [p]
         L.blco_free.restype = None
         L.blco_last_error.restype = ctypes.c_char_p
@@ -170,6 +172,12 @@ class BLCOTensor:
         c = ctypes.c_int(-1)
         _check(lib().blco_resolution(self._h, int(mode), int(rank), ctypes.byref(c)))
         return {v: k for k, v in RESOLUTIONS.items()}[c.value]
+
+    def stash_rows(self, mode: int, rank: int) -> int:
+        """Frequent rows of `mode` a register-based MTTKRP at `rank` sums in its LDS stash."""
+        c = ctypes.c_int(-1)
+        _check(lib().blco_frequent_rows(self._h, int(mode), int(rank), ctypes.byref(c)))
+        return c.value
 
     def export(self):
         """(keys uint64, values float32, block_ids uint64, block_starts int64) on the host."""
@@ -374,6 +382,19 @@ def cast_bf16(x, stream=None):
     y = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
     _check(lib().blco_cast_bf16(x.data_ptr(), y.data_ptr(), x.numel(), _stream(stream)))
     return y
+
+
+def atomic_probe(out, rows, stream=None):
+    """Calibration kernel: out[rows[k], :] += 1 with one device-scope fp32 atomic per entry
+    (16-lane groups, the MTTKRP kernels' flush pattern).  out: float32 (I x R) device
+    tensor; rows: int32 device tensor of row ids (uint32 bits)."""
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.dim() != 2:
+        raise ValueError("out must be a contiguous 2-D float32 tensor")
+    if rows.dtype != torch.int32 or not rows.is_contiguous():
+        raise ValueError("rows must be a contiguous int32 tensor")
+    _check(lib().blco_atomic_probe(out.data_ptr(), out.shape[0], out.shape[1], rows.data_ptr(),
+                                   rows.numel(), _stream(stream)))
+    return out
 
 
 def gram(A, stream=None):

@@ -1,19 +1,28 @@
 // Device runtime and gfx950 kernels of the BLCO sparse MTTKRP library.
 //
 // Method: Nguyen et al., "Efficient, Out-of-Memory Sparse MTTKRP on Massively
-// Parallel Architectures", ICS '22.  The MTTKRP kernel follows the
-// processing / computing split of Section 5.1 (Figure 7) with the
-// register-based conflict resolution of Section 5.2, re-designed for wave64:
-//   processing: each lane of a wave loads one (key, value) pair (coalesced),
-//     decodes every coordinate by shift and mask (Figure 6b), and the wave
-//     sorts its 64 non-zeros by target index with a bitonic network of
-//     cross-lane exchanges, so equal targets become contiguous segments whose
-//     ends form a 64-bit mask;
-//   computing: lanes are reassigned along the rank, one group of LPN lanes
-//     per non-zero; a group walks its run of sorted non-zeros, gathers the
-//     factor rows of the other modes, accumulates the scaled Hadamard product
-//     in a register while the target is unchanged and issues one atomic add
-//     per (segment, rank) at each segment end.
+// Parallel Architectures", ICS '22.  Two MTTKRP kernels follow the processing /
+// computing split of Section 5.1 (Figure 7), re-designed for wave64 and the
+// memory-side atomics of MI355X:
+//   k_mttkrp_win (register-based resolution, Section 5.2): one 1024-thread
+//     workgroup per window of 1024 consecutive non-zeros.  Processing: each
+//     thread loads one (key, value) pair (coalesced), decodes the coordinates
+//     by shift and mask (Figure 6b), and the window is grouped by target row
+//     with a counting sort on a hash of the target (LDS histogram, workgroup
+//     scan, scatter), so each target forms one segment; every grouped position
+//     gets a record (byte offsets of the other modes' rows, target, value).
+//     Computing: groups of 16 lanes (1-4 ranks per lane) walk the records,
+//     gather the factor rows with raw buffer loads, sum the scaled Hadamard
+//     products in registers while the target repeats, and add each finished
+//     segment to the output with one atomic per rank.  A mode's frequent rows
+//     (found at build time) are summed in an LDS stash instead and flushed
+//     once per persistent workgroup.
+//   k_mttkrp_short (hierarchical resolution, Section 5.1), which the Section
+//     5.3 heuristic picks for modes shorter than the compute-unit count: each
+//     workgroup keeps a private LDS copy of all target rows (a rank slice) and
+//     adds it to the output once at its end.
+// Also here: the sampled CP model / residual / fp64 loss kernels, the bf16
+// cast, the out-of-memory streaming runtime and the C ABI of include/blco.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -67,39 +76,6 @@ __device__ __forceinline__ void decode(const KParams& p, uint64_t key, int64_t g
   for (int m = 0; m < N; ++m) c[m] = ((uint32_t)(key >> p.shift[m]) & p.mask[m]) | base[m];
 }
 
-// Ascending bitonic sort of one 32-bit value per lane across the wave.
-__device__ __forceinline__ uint32_t wave_sort32(uint32_t v, int lane) {
-#pragma unroll
-  for (int size = 2; size <= 64; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      uint32_t o = (uint32_t)__shfl_xor((int)v, stride);
-      bool asc = (lane & size) == 0;
-      bool lower = (lane & stride) == 0;
-      uint32_t mn = min(v, o), mx = max(v, o);
-      v = (asc == lower) ? mn : mx;
-    }
-  }
-  return v;
-}
-
-__device__ __forceinline__ uint64_t wave_sort64(uint64_t v, int lane) {
-#pragma unroll
-  for (int size = 2; size <= 64; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, stride);
-      uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), stride);
-      uint64_t o = ((uint64_t)hi << 32) | lo;
-      bool asc = (lane & size) == 0;
-      bool lower = (lane & stride) == 0;
-      uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
-      v = (asc == lower) ? mn : mx;
-    }
-  }
-  return v;
-}
-
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -121,123 +97,6 @@ __global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, int64_
     for (int64_t j = (n4 << 2) + i; j < n; j += stride) p[j] = 0.f;
   } else {
     for (int64_t j = i; j < n; j += stride) p[j] = 0.f;
-  }
-}
-
-// Reference-shaped kernel: one thread per (non-zero, rank), one atomic each.
-// Kept as the ablation point for the conflict resolution of the tile kernel.
-template <typename FT, int N>
-__global__ __launch_bounds__(256) void k_mttkrp_naive(KParams p) {
-  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t k = gid / p.R;
-  const int r = (int)(gid - k * p.R);
-  if (k >= p.n) return;
-  uint32_t c[N];
-  decode<N>(p, p.keys[k], p.base + k, c);
-  float v = p.vals[k] * term_scale(p);
-  uint32_t tgt = 0;
-#pragma unroll
-  for (int m = 0; m < N; ++m) {
-    if (m == p.mode) {
-      tgt = c[m];
-    } else {
-      v *= ld_factor<FT>(p.A[m], (size_t)c[m] * p.R + r);
-    }
-  }
-  unsafeAtomicAdd(p.out + (size_t)tgt * p.R + r, v);
-}
-
-// BLCO MTTKRP, register-based conflict resolution (Sections 5.1-5.2).
-// One wave per tile of 64 consecutive non-zeros; LPN lanes per non-zero in the
-// computing phase, LPN non-zeros walked by each group.
-template <int LPN, typename FT, int N>
-__global__ __launch_bounds__(kBlock) void k_mttkrp_tile(KParams p) {
-  constexpr int G = 64 / LPN;    // groups per wave
-  constexpr int PPG = 64 / G;    // sorted positions per group
-  constexpr int NF = N + 1;      // coordinates + value
-  constexpr int U = PPG < 8 ? PPG : 8;
-  __shared__ uint32_t s[kWaves][64][NF];
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t tile = (int64_t)blockIdx.x * kWaves + wv;
-  if (tile * 64 >= p.n) return;
-  const int64_t k = tile * 64 + lane;
-  const int nvalid = (int)min((int64_t)64, p.n - tile * 64);
-  const bool valid = lane < nvalid;
-
-  // processing phase: load, decode, sort by target, stage in sorted order
-  uint32_t c[N];
-  float x = 0.f;
-  if (valid) {
-    uint64_t key = p.keys[k];
-    x = p.vals[k];
-    decode<N>(p, key, p.base + k, c);
-  } else {
-#pragma unroll
-    for (int m = 0; m < N; ++m) c[m] = 0;
-  }
-  uint32_t tgt = 0;
-#pragma unroll
-  for (int m = 0; m < N; ++m)
-    if (m == p.mode) tgt = c[m];
-  int src;
-  uint32_t stgt;
-  if (!p.wide) {
-    uint32_t v = valid ? ((tgt << 6) | (uint32_t)lane) : 0xFFFFFFFFu;
-    v = wave_sort32(v, lane);
-    src = (int)(v & 63);
-    stgt = v >> 6;
-  } else {
-    uint64_t v = valid ? (((uint64_t)tgt << 6) | (uint64_t)lane) : ~0ULL;
-    v = wave_sort64(v, lane);
-    src = (int)(v & 63);
-    stgt = (uint32_t)(v >> 6);
-  }
-#pragma unroll
-  for (int m = 0; m < N; ++m) s[wv][lane][m] = (uint32_t)__shfl((int)c[m], src);
-  s[wv][lane][N] = (uint32_t)__shfl((int)__float_as_uint(x), src);
-  const uint32_t nxt = (uint32_t)__shfl((int)stgt, (lane + 1) & 63);
-  const bool end = (lane == nvalid - 1) || (lane < nvalid - 1 && nxt != stgt);
-  const uint64_t endm = __ballot(end);
-  wave_sync_lds();
-
-  // computing phase: rank-wise accumulate, flush at segment ends
-  const int g = lane / LPN;
-  const int rl = lane % LPN;
-  const float scale = term_scale(p);
-  const int R = p.R;
-  for (int r0 = 0; r0 < R; r0 += LPN) {
-    const int r = r0 + rl;
-    const bool ract = r < R;
-    const int rr = ract ? r : 0;
-    float acc = 0.f;
-    for (int q0 = 0; q0 < PPG; q0 += U) {
-      float pr[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t* e = s[wv][g * PPG + q0 + u];
-        float v = __uint_as_float(e[N]);
-#pragma unroll
-        for (int m = 0; m < N; ++m)
-          if (m != p.mode) v *= ld_factor<FT>(p.A[m], (size_t)e[m] * R + rr);
-        pr[u] = v;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int pidx = g * PPG + q0 + u;
-        acc += pr[u];
-        if (((endm >> pidx) & 1) || (q0 + u == PPG - 1)) {
-          if (ract && pidx < nvalid) {
-            uint32_t t = 0;
-#pragma unroll
-            for (int m = 0; m < N; ++m)
-              if (m == p.mode) t = s[wv][pidx][m];
-            unsafeAtomicAdd(p.out + (size_t)t * R + r, acc * scale);
-          }
-          acc = 0.f;
-        }
-      }
-    }
   }
 }
 
@@ -885,241 +744,6 @@ __global__ __launch_bounds__(kShortB, 8) void k_mttkrp_short(KParams p, int64_t 
   }
 }
 
-// ---------------------------------------------------------------------------
-// BLCO MTTKRP with hierarchical conflict resolution through a hashed LDS stash
-// (Section 5.1, steps 5-6) for target modes of any length; a variant kept for
-// comparison (BLCO_KERNEL=stash).
-//
-// Persistent workgroups of kSB threads each own a contiguous range of the
-// ALTO-ordered non-zeros and walk it in batches of kSB:
-//   processing: one non-zero per thread is loaded (coalesced) and decoded by
-//     shift and mask; its target row is looked up in an LDS hash table that
-//     maps target -> dense segment id, claiming a new segment when the target
-//     is new to the current window;
-//   computing: LG lanes per non-zero, each holding V consecutive ranks, gather
-//     the other modes' factor rows (one V-wide load per factor), form the
-//     scaled Hadamard product and add it into the segment's LDS accumulator;
-//   flushing: once the stash holds S segments (or the range ends) every
-//     segment row is added to the output with one global atomic per
-//     (segment, rank), and the stash is cleared.
-// Equal targets inside a window therefore cost one global atomic each; a
-// target that arrives when the stash is full is added straight to the output.
-constexpr int kSB = 512;               // threads per workgroup = non-zeros per batch
-constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-constexpr uint32_t kOverflow = 0xFFFFFFFEu;
-
-struct StashCfg {
-  int S;        // segment rows in the stash
-  int TS;       // hash table slots (power of two >= 2 S)
-  int tsbits;
-  int lg_log;   // log2 of lanes per non-zero in the computing phase
-  int Rp;       // stash row length (R rounded up to LG * V)
-  int64_t per;  // non-zeros per workgroup range (multiple of kSB)
-};
-
-template <int V, typename FT>
-struct Vec;
-template <>
-struct Vec<1, float> {
-  static __device__ __forceinline__ void load(const void* A, size_t i, float* o) {
-    o[0] = static_cast<const float*>(A)[i];
-  }
-};
-template <>
-struct Vec<4, float> {
-  static __device__ __forceinline__ void load(const void* A, size_t i, float* o) {
-    const float4 v = *reinterpret_cast<const float4*>(static_cast<const float*>(A) + i);
-    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-  }
-};
-template <>
-struct Vec<1, uint16_t> {
-  static __device__ __forceinline__ void load(const void* A, size_t i, float* o) {
-    o[0] = __uint_as_float((uint32_t)static_cast<const uint16_t*>(A)[i] << 16);
-  }
-};
-template <>
-struct Vec<4, uint16_t> {
-  static __device__ __forceinline__ void load(const void* A, size_t i, float* o) {
-    const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(A) + i);
-    o[0] = __uint_as_float(v.x << 16);
-    o[1] = __uint_as_float(v.x & 0xFFFF0000u);
-    o[2] = __uint_as_float(v.y << 16);
-    o[3] = __uint_as_float(v.y & 0xFFFF0000u);
-  }
-};
-
-__device__ __forceinline__ uint32_t stash_hash(uint32_t t, int bits) {
-  return (t * 0x9E3779B1u) >> (32 - bits);
-}
-
-template <int V, typename FT, int N>
-__global__ __launch_bounds__(kSB) void k_mttkrp_stash(KParams p, StashCfg cfg) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  // LDS layout: accumulators | segment targets | table keys | table values |
-  //             batch coordinates | batch values | batch segment ids | counter
-  float* s_acc = reinterpret_cast<float*>(smem);
-  uint32_t* s_segt = reinterpret_cast<uint32_t*>(s_acc + (size_t)cfg.S * cfg.Rp);
-  uint32_t* s_tkey = s_segt + cfg.S;
-  uint32_t* s_tval = s_tkey + cfg.TS;
-  uint32_t* s_c = s_tval + cfg.TS;            // N x kSB
-  float* s_x = reinterpret_cast<float*>(s_c + N * kSB);
-  uint32_t* s_sid = reinterpret_cast<uint32_t*>(s_x + kSB);
-  uint32_t* s_nseg = s_sid + kSB;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int R = p.R;
-  const int Rp = cfg.Rp;
-  const float scale = term_scale(p);
-  const int64_t lo = (int64_t)blockIdx.x * cfg.per;
-  const int64_t hi = min(p.n, lo + cfg.per);
-  if (lo >= hi) return;
-
-  for (int i = tid; i < cfg.S * Rp; i += kSB) s_acc[i] = 0.f;
-  for (int i = tid; i < cfg.TS; i += kSB) s_tkey[i] = kEmpty;
-  if (tid == 0) *s_nseg = 0;
-  __syncthreads();
-
-  const int LG = 1 << cfg.lg_log;               // lanes per non-zero
-  const int NG = kSB >> cfg.lg_log;             // non-zeros in flight per workgroup step
-  const int gi = tid >> cfg.lg_log;             // group of this lane
-  const int gl = tid & (LG - 1);                // lane within the group
-
-  for (int64_t b0 = lo; b0 < hi; b0 += kSB) {
-    // ---- processing: load, decode, find or claim the target's segment
-    const int64_t k = b0 + tid;
-    const bool valid = k < hi;
-    uint32_t c[N];
-    float x = 0.f;
-    if (valid) {
-      const uint64_t key = p.keys[k];
-      x = p.vals[k];
-      decode<N>(p, key, p.base + k, c);
-    } else {
-#pragma unroll
-      for (int m = 0; m < N; ++m) c[m] = 0;
-    }
-    uint32_t tgt = 0;
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-      s_c[m * kSB + tid] = c[m];
-      if (m == p.mode) tgt = c[m];
-    }
-    s_x[tid] = x;
-    int slot = -1;
-    bool claimed = false;
-    if (valid && tgt < kOverflow) {
-      uint32_t h = stash_hash(tgt, cfg.tsbits);
-      for (int probe = 0; probe < 32; ++probe) {
-        const uint32_t old = atomicCAS(&s_tkey[h], kEmpty, tgt);
-        if (old == kEmpty || old == tgt) {
-          slot = (int)h;
-          claimed = old == kEmpty;
-          break;
-        }
-        h = (h + 1) & (uint32_t)(cfg.TS - 1);
-      }
-    }
-    __syncthreads();
-    // segment ids for newly claimed slots: one LDS atomic per wave
-    const uint64_t cm = __ballot(claimed);
-    uint32_t base = 0;
-    if (lane == 0 && cm) base = atomicAdd(s_nseg, (uint32_t)__popcll(cm));
-    base = (uint32_t)__shfl((int)base, 0);
-    if (claimed) {
-      const uint32_t sid = base + (uint32_t)__popcll(cm & ((1ULL << lane) - 1));
-      if (sid < (uint32_t)cfg.S) {
-        s_tval[slot] = sid;
-        s_segt[sid] = tgt;
-      } else {
-        s_tval[slot] = kOverflow;
-      }
-    }
-    __syncthreads();
-    s_sid[tid] = valid ? (slot >= 0 ? s_tval[slot] : kOverflow) : kEmpty;
-    __syncthreads();
-
-    // ---- computing: LG lanes per non-zero, V ranks per lane
-    for (int r0 = 0; r0 < R; r0 += LG * V) {
-      const int rbase = r0 + gl * V;
-      for (int j = gi; j < kSB; j += NG) {
-        const uint32_t sid = s_sid[j];
-        if (sid == kEmpty) continue;
-        float v[V];
-        const float xv = s_x[j];
-#pragma unroll
-        for (int e = 0; e < V; ++e) v[e] = xv;
-        if (rbase < R) {
-#pragma unroll
-          for (int m = 0; m < N; ++m) {
-            if (m == p.mode) continue;
-            const size_t row = (size_t)s_c[m * kSB + j] * R;
-            if (V == 1 || rbase + V <= R) {
-              float f[V];
-              Vec<V, FT>::load(p.A[m], row + rbase, f);
-#pragma unroll
-              for (int e = 0; e < V; ++e) v[e] *= f[e];
-            } else {
-#pragma unroll
-              for (int e = 0; e < V; ++e) {
-                float f1[1];
-                Vec<1, FT>::load(p.A[m], row + (rbase + e < R ? rbase + e : 0), f1);
-                v[e] *= f1[0];
-              }
-            }
-          }
-        }
-        if (sid < (uint32_t)cfg.S) {
-          float* a = s_acc + (size_t)sid * Rp + rbase - r0;
-#pragma unroll
-          for (int e = 0; e < V; ++e)
-            if (rbase + e < R) atomicAdd(a + e, v[e]);
-        } else {
-          const uint32_t t = s_c[p.mode * kSB + j];
-#pragma unroll
-          for (int e = 0; e < V; ++e)
-            if (rbase + e < R) unsafeAtomicAdd(p.out + (size_t)t * R + rbase + e, v[e] * scale);
-        }
-      }
-      if (r0 + LG * V < R) {
-        // next rank chunk reuses the accumulators: flush this chunk first
-        __syncthreads();
-        const int nseg = min((int)*s_nseg, cfg.S);
-        for (int i = tid; i < nseg * LG * V; i += kSB) {
-          const int sgi = i / (LG * V), rr = i % (LG * V);
-          if (r0 + rr < R) {
-            float* a = s_acc + (size_t)sgi * Rp + rr;
-            const float val = *a;
-            if (val != 0.f) unsafeAtomicAdd(p.out + (size_t)s_segt[sgi] * R + r0 + rr, val * scale);
-            *a = 0.f;
-          }
-        }
-        __syncthreads();
-      }
-    }
-    __syncthreads();
-    // ---- flush the stash when full or at the end of the range
-    const int nseg_all = (int)*s_nseg;
-    if (nseg_all >= cfg.S || b0 + kSB >= hi) {
-      const int nseg = min(nseg_all, cfg.S);
-      const int rlast = ((R - 1) / (LG * V)) * (LG * V);  // rank chunk still held
-      const int w = min(R - rlast, LG * V);
-      for (int i = tid; i < nseg * w; i += kSB) {
-        const int sgi = i / w, rr = i - sgi * w;
-        float* a = s_acc + (size_t)sgi * Rp + rr;
-        const float val = *a;
-        if (val != 0.f) unsafeAtomicAdd(p.out + (size_t)s_segt[sgi] * R + rlast + rr, val * scale);
-        *a = 0.f;
-      }
-      for (int i = tid; i < cfg.TS; i += kSB) s_tkey[i] = kEmpty;
-      __syncthreads();
-      if (tid == 0) *s_nseg = 0;
-      __syncthreads();
-    }
-  }
-}
-
 // Sampled CP model, residual and squared residual sums (Section 2.2 model):
 // one wave per 64 consecutive non-zeros.  Each non-zero's record (byte offsets,
 // or row indices when BIG, of its N factor rows, and its value) goes to LDS;
@@ -1256,23 +880,25 @@ __global__ __launch_bounds__(256) void k_cast_bf16(const float* __restrict__ src
   }
 }
 
+// Calibration of the memory-side atomic rate: for each k < n, one row-op on
+// out row rows[k]: 16 lanes add 1.0f to the row's R entries, lane l holding
+// ranks l, l + 16, ..., as the window kernel flushes a finished segment.  Row
+// ids at or past nrows are skipped.
+__global__ __launch_bounds__(256) void k_atomic_probe(float* __restrict__ out, int64_t nrows,
+                                                      const uint32_t* __restrict__ rows,
+                                                      int64_t n, int R) {
+  const int64_t g = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
+  const int rl = threadIdx.x & 15;
+  if (g >= n) return;
+  const uint32_t row = rows[g];
+  if ((int64_t)row >= nrows) return;
+  float* dst = out + (size_t)row * R;
+  for (int r = rl; r < R; r += 16) unsafeAtomicAdd(dst + r, 1.0f);
+}
+
 // ====================================================================== dispatch
 
 typedef void (*KernelFn)(KParams);
-
-template <int LPN, typename FT>
-static KernelFn pick_tile(int N) {
-  switch (N) {
-    case 1: return k_mttkrp_tile<LPN, FT, 1>;
-    case 2: return k_mttkrp_tile<LPN, FT, 2>;
-    case 3: return k_mttkrp_tile<LPN, FT, 3>;
-    case 4: return k_mttkrp_tile<LPN, FT, 4>;
-    case 5: return k_mttkrp_tile<LPN, FT, 5>;
-    case 6: return k_mttkrp_tile<LPN, FT, 6>;
-    case 7: return k_mttkrp_tile<LPN, FT, 7>;
-    default: return k_mttkrp_tile<LPN, FT, 8>;
-  }
-}
 
 template <int LPN, int RPL, typename FT, bool BIG, bool STASH>
 static KernelFn pick_win_s(int N) {
@@ -1293,7 +919,6 @@ static KernelFn pick_win(int N, bool stash) {
   return stash ? pick_win_s<LPN, RPL, FT, BIG, true>(N) : pick_win_s<LPN, RPL, FT, BIG, false>(N);
 }
 
-typedef void (*StashFn)(KParams, StashCfg);
 typedef void (*ShortFn)(KParams, int64_t);
 
 template <int RPL, typename FT, bool BIG>
@@ -1358,20 +983,6 @@ static int device_cus() {
   return cached[dev];
 }
 
-template <int V, typename FT>
-static StashFn pick_stash(int N) {
-  switch (N) {
-    case 1: return k_mttkrp_stash<V, FT, 1>;
-    case 2: return k_mttkrp_stash<V, FT, 2>;
-    case 3: return k_mttkrp_stash<V, FT, 3>;
-    case 4: return k_mttkrp_stash<V, FT, 4>;
-    case 5: return k_mttkrp_stash<V, FT, 5>;
-    case 6: return k_mttkrp_stash<V, FT, 6>;
-    case 7: return k_mttkrp_stash<V, FT, 7>;
-    default: return k_mttkrp_stash<V, FT, 8>;
-  }
-}
-
 template <int RPL, typename FT, bool BIG>
 static KernelFn pick_loss(int N) {
   switch (N) {
@@ -1384,35 +995,6 @@ static KernelFn pick_loss(int N) {
     case 7: return k_loss_tile<RPL, FT, 7, BIG>;
     default: return k_loss_tile<RPL, FT, 8, BIG>;
   }
-}
-
-template <typename FT>
-static KernelFn pick_naive(int N) {
-  switch (N) {
-    case 1: return k_mttkrp_naive<FT, 1>;
-    case 2: return k_mttkrp_naive<FT, 2>;
-    case 3: return k_mttkrp_naive<FT, 3>;
-    case 4: return k_mttkrp_naive<FT, 4>;
-    case 5: return k_mttkrp_naive<FT, 5>;
-    case 6: return k_mttkrp_naive<FT, 6>;
-    case 7: return k_mttkrp_naive<FT, 7>;
-    default: return k_mttkrp_naive<FT, 8>;
-  }
-}
-
-// lanes per non-zero in the computing phase: the rank rounded up to 16, 32 or 64
-static int lanes_per_nnz(int R) { return R <= 16 ? 16 : (R <= 32 ? 32 : 64); }
-
-static KernelFn select_tile(int N, int R, int fdt) {
-  int lpn = lanes_per_nnz(R);
-  if (fdt == BLCO_F32) {
-    if (lpn == 16) return pick_tile<16, float>(N);
-    if (lpn == 32) return pick_tile<32, float>(N);
-    return pick_tile<64, float>(N);
-  }
-  if (lpn == 16) return pick_tile<16, uint16_t>(N);
-  if (lpn == 32) return pick_tile<32, uint16_t>(N);
-  return pick_tile<64, uint16_t>(N);
 }
 
 // window kernel shape (lanes per non-zero x ranks per lane), chosen by measurement on
@@ -1443,40 +1025,6 @@ static KernelFn select_loss(int N, int R, int fdt, bool big) {
   if (fdt == BLCO_F32)
     return big ? select_loss_t<float, true>(N, R) : select_loss_t<float, false>(N, R);
   return big ? select_loss_t<uint16_t, true>(N, R) : select_loss_t<uint16_t, false>(N, R);
-}
-
-// MTTKRP kernel variant, chosen once per process from BLCO_KERNEL:
-//   "win" (default): 1024-non-zero windows grouped per workgroup;
-//   "stash": persistent workgroups with a hashed LDS segment stash;
-//   "tile": 64-non-zero tiles sorted per wave;
-//   "naive": one thread and one atomic per (non-zero, rank).
-enum { kVarWin = 0, kVarStash = 1, kVarTile = 2, kVarNaive = 3 };
-static int g_variant = -1;
-
-// LDS bytes per workgroup for the stash kernel (BLCO_STASH_KB, default 64)
-static size_t stash_lds_budget() {
-  const char* e = getenv("BLCO_STASH_KB");
-  long kb = e ? atol(e) : 64;
-  if (kb < 16) kb = 16;
-  if (kb > 160) kb = 160;
-  return (size_t)kb * 1024;
-}
-
-// workgroups the non-zeros are split over (BLCO_STASH_WG, default 2048)
-static int64_t stash_workgroups() {
-  const char* e = getenv("BLCO_STASH_WG");
-  long w = e ? atol(e) : 2048;
-  return w < 1 ? 1 : w;
-}
-static int kernel_variant() {
-  if (g_variant < 0) {
-    const char* e = getenv("BLCO_KERNEL");
-    g_variant = kVarWin;
-    if (e && strcmp(e, "stash") == 0) g_variant = kVarStash;
-    if (e && strcmp(e, "naive") == 0) g_variant = kVarNaive;
-    if (e && strcmp(e, "tile") == 0) g_variant = kVarTile;
-  }
-  return g_variant;
 }
 
 // Conflict-resolution mechanism of a mode-`mode` MTTKRP at rank R (Section
@@ -1578,6 +1126,27 @@ static int check_factor_args(const blco_tensor* t, int mode, const void* const* 
   return res < 0 ? res : BLCO_OK;
 }
 
+// Frequent rows of the target mode that the window kernel `f` keeps in its
+// LDS stash: as many as fit beside the kernel's own LDS in one workgroup's
+// share of a CU, or none when the rows left out would not be much less
+// frequent than the most frequent one (a stash shortens the longest atomic
+// chains only then: measured slower on a 1024-row uniform mode, where a fifth
+// of the rows fit).  An explicit threshold at build time keeps the stash
+// regardless.  The kernel's static LDS does not depend on the factor type.
+static int stash_rows(const blco_tensor* t, int mode, int rank, KernelFn f) {
+  if (t->nhot[mode] <= 0 || !t->d_hot) return 0;
+  int K = 0;
+  const size_t fixed = kernel_static_lds((const void*)f) + 2 * (size_t)kHotSlots * 4;
+  const size_t budget = win_lds_budget();
+  if (budget > fixed)
+    K = (int)std::min<size_t>((size_t)t->nhot[mode], (budget - fixed) / ((size_t)rank * 4));
+  if (K > 0 && !t->hot_forced) {
+    const uint64_t* cnt = t->hot_cnt.data() + (size_t)mode * (kHotMax + 1);
+    if (cnt[K] * 4 > cnt[0]) K = 0;
+  }
+  return K;
+}
+
 // Launch the MTTKRP kernel over [lo, lo + n) of the tensor given by keys/vals.
 static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float* vals,
                          int64_t lo, int64_t n, int mode, const void* const* factors, int fdt,
@@ -1594,10 +1163,8 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
   p.out = out;
   p.R = rank;
   p.mode = mode;
-  p.wide = t->lay.dims[mode] > ((1ULL << 26) - 1) ? 1 : 0;
   p.scale = scale;
   p.scale_dev = scale_dev;
-  int var = kernel_variant();
   const size_t fsz = factor_elem_bytes(fdt);
   p.rowbytes = (uint32_t)((size_t)rank * fsz);
   // factors below 4 GiB are gathered with 32-bit byte offsets, larger ones
@@ -1626,65 +1193,10 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
     HIPCHK(hipGetLastError());
     return BLCO_OK;
   }
-  if (var == kVarNaive) {
-    int64_t threads = n * (int64_t)rank;
-    int64_t blocks = (threads + 255) / 256;
-    KernelFn f = (fdt == BLCO_F32) ? pick_naive<float>(t->lay.N) : pick_naive<uint16_t>(t->lay.N);
-    hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, s, p);
-  } else if (var == kVarStash) {
-    const int N = t->lay.N;
-    const int V = (rank % 4 == 0) ? 4 : 1;
-    int lanes = (rank + V - 1) / V;
-    int lg_log = 0;
-    while ((1 << lg_log) < lanes && lg_log < 6) ++lg_log;
-    StashCfg cfg;
-    cfg.lg_log = lg_log;
-    cfg.Rp = (1 << lg_log) * V;
-    const size_t budget = stash_lds_budget();
-    const size_t fixed = (size_t)(N + 2) * kSB * 4 + 16;
-    int bestS = 0, bestTS = 0;
-    for (int TS = 4096; TS >= 256; TS >>= 1) {
-      if (fixed + (size_t)TS * 8 >= budget) continue;
-      size_t avail = budget - fixed - (size_t)TS * 8;
-      int S = (int)std::min<size_t>((size_t)TS / 2, avail / ((size_t)cfg.Rp * 4 + 4));
-      if (S > bestS) { bestS = S; bestTS = TS; }
-    }
-    if (bestS < 1) return set_error(BLCO_EUNSUPPORTED, "rank %d too large for the LDS stash", rank);
-    cfg.S = bestS;
-    cfg.TS = bestTS;
-    cfg.tsbits = 0;
-    while ((1 << cfg.tsbits) < cfg.TS) ++cfg.tsbits;
-    const int64_t batches = (n + kSB - 1) / kSB;
-    const int64_t want_wg = stash_workgroups();
-    int64_t per_b = std::max<int64_t>((batches + want_wg - 1) / want_wg, 1);
-    cfg.per = per_b * kSB;
-    const int64_t nwg = (n + cfg.per - 1) / cfg.per;
-    const size_t lds = (size_t)cfg.S * cfg.Rp * 4 + (size_t)cfg.S * 4 + (size_t)cfg.TS * 8 +
-                       (size_t)(N + 2) * kSB * 4 + 16;
-    StashFn f = (fdt == BLCO_F32) ? (V == 4 ? pick_stash<4, float>(N) : pick_stash<1, float>(N))
-                                  : (V == 4 ? pick_stash<4, uint16_t>(N) : pick_stash<1, uint16_t>(N));
-    if (lds > 65536) HIPCHK(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(f, dim3((unsigned)nwg), dim3(kSB), lds, s, p, cfg);
-  } else if (var == kVarWin) {
+  {
     KernelFn f = select_win(t->lay.N, rank, fdt, big, true);
     const int64_t nwin = (n + kWin - 1) / kWin;
-    // frequent rows of the target mode kept in the LDS stash: as many as fit
-    // beside the kernel's own LDS in one workgroup's share of a CU
-    int K = 0;
-    if (t->nhot[mode] > 0 && t->d_hot) {
-      const size_t fixed = kernel_static_lds((const void*)f) + 2 * (size_t)kHotSlots * 4;
-      const size_t budget = win_lds_budget();
-      if (budget > fixed)
-        K = (int)std::min<size_t>((size_t)t->nhot[mode], (budget - fixed) / ((size_t)rank * 4));
-      // a stash shortens the longest atomic chains only if the rows left out
-      // are much less frequent than the most frequent one (measured slower on
-      // a 1024-row uniform mode, where a fifth of the rows fit); an explicit
-      // threshold at build time keeps the stash regardless
-      if (K > 0 && !t->hot_forced) {
-        const uint64_t* cnt = t->hot_cnt.data() + (size_t)mode * (kHotMax + 1);
-        if (cnt[K] * 4 > cnt[0]) K = 0;
-      }
-    }
+    const int K = stash_rows(t, mode, rank, f);
     p.hot = t->d_hot + (size_t)mode * kHotMax;
     p.nhot = K;
     if (K == 0) f = select_win(t->lay.N, rank, fdt, big, false);
@@ -1696,11 +1208,6 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
     const int64_t grid =
         K > 0 ? std::min<int64_t>(nwin, (int64_t)device_cus() * 2 * kWinRounds) : nwin;
     hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kWin), dyn, s, p);
-  } else {
-    int64_t tiles = (n + 63) / 64;
-    int64_t blocks = (tiles + kWaves - 1) / kWaves;
-    KernelFn f = select_tile(t->lay.N, rank, fdt);
-    hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(kBlock), 0, s, p);
   }
   HIPCHK(hipGetLastError());
   return BLCO_OK;
@@ -2038,12 +1545,20 @@ extern "C" int blco_sampled_loss(blco_tensor* t, const void* const* factors, int
     return set_error(BLCO_EINVAL, "factor dtype %d", factor_dtype);
   if (!factors) return set_error(BLCO_EINVAL, "factors is NULL");
   for (int m = 0; m < t->lay.N; ++m)
-    if (!factors[m] && t->nnz > 0) return set_error(BLCO_EINVAL, "factors[%d] is NULL", m);
+    if (!factors[m]) return set_error(BLCO_EINVAL, "factors[%d] is NULL", m);
   if (t->placement != BLCO_PLACE_DEVICE)
     return set_error(BLCO_EINVAL, "the sampled loss needs a tensor placed on the device");
   hipStream_t s = (hipStream_t)stream;
+  if (t->nnz == 0) {
+    // no non-zeros: the loss is 0 (the reduction over zero partials writes it),
+    // and no factor row is gathered
+    hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(1024), 0, s, (const double*)nullptr,
+                       (int64_t)0, loss);
+    HIPCHK(hipGetLastError());
+    return BLCO_OK;
+  }
   int64_t tiles = (t->nnz + 63) / 64;
-  int64_t blocks = std::max<int64_t>((tiles + kWaves - 1) / kWaves, 1);
+  int64_t blocks = (tiles + kWaves - 1) / kWaves;
   if (t->partials_cap < blocks) {
     if (t->d_partials) {
       HIPCHK(hipStreamSynchronize(s));
@@ -2084,6 +1599,21 @@ extern "C" int blco_sampled_loss(blco_tensor* t, const void* const* factors, int
   return BLCO_OK;
 }
 
+extern "C" int blco_atomic_probe(float* out, int64_t nrows, int rank, const uint32_t* rows,
+                                 int64_t n, void* stream) {
+  clear_error();
+  if (n < 0 || nrows < 0) return set_error(BLCO_EINVAL, "negative size");
+  if (rank < 1) return set_error(BLCO_EINVAL, "rank %d < 1", rank);
+  if (n == 0) return BLCO_OK;
+  if (!out || !rows) return set_error(BLCO_EINVAL, "out or rows is NULL");
+  const int64_t blocks = (n * 16 + 255) / 256;
+  if (blocks > 0x7FFFFFFF) return set_error(BLCO_EINVAL, "n = %lld too large", (long long)n);
+  hipLaunchKernelGGL(k_atomic_probe, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                     out, nrows, rows, n, rank);
+  HIPCHK(hipGetLastError());
+  return BLCO_OK;
+}
+
 extern "C" int blco_set_resolution(blco_tensor* t, int resolution) {
   clear_error();
   if (!t) return set_error(BLCO_EINVAL, "tensor is NULL");
@@ -2105,6 +1635,16 @@ extern "C" int blco_resolution(const blco_tensor* t, int mode, int rank, int* ch
   const int res = resolve(t, mode, rank, &sw);
   if (res < 0) return res;
   *chosen = res;
+  return BLCO_OK;
+}
+
+extern "C" int blco_frequent_rows(const blco_tensor* t, int mode, int rank, int* rows) {
+  clear_error();
+  if (!t || !rows) return set_error(BLCO_EINVAL, "tensor or rows is NULL");
+  if (mode < 0 || mode >= t->lay.N)
+    return set_error(BLCO_EINVAL, "mode %d outside 0..%d", mode, t->lay.N - 1);
+  if (rank < 1) return set_error(BLCO_EINVAL, "rank %d < 1", rank);
+  *rows = stash_rows(t, mode, rank, select_win(t->lay.N, rank, BLCO_F32, false, true));
   return BLCO_OK;
 }
 

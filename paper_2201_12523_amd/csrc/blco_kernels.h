@@ -28,7 +28,6 @@ struct KParams {
   int mode;
   uint32_t shift[8];
   uint32_t mask[8];
-  int wide;                   // target index too long for 32-bit sort keys
   const uint32_t* hot;        // window kernel: frequent rows of the target mode
   int nhot;                   // window kernel: frequent rows held in the LDS stash
   uint32_t short_rows;        // hierarchical kernel: target mode length

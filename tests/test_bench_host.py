@@ -45,48 +45,49 @@ def test_kernel_names(bench):
     assert bench.short_kernel_name(32, 4) == "k_mttkrp_short<2, float, 4, false>"
 
 
-def test_traffic_scaled_by_the_copy(bench, tmp_path):
-    k = "void " + bench.win_kernel_name(32, 3)
-    fetch, write, out = tmp_path / "f.csv", tmp_path / "w.csv", tmp_path / "t.txt"
+def test_counters_traffic_and_atomics(bench, tmp_path):
+    """Per-dispatch means per kernel, the copy-calibrated HBM traffic and the row-ops derived
+    from TCC_EA0_ATOMIC with the probe kernel as the per-row-op reference."""
+    k = "void " + bench.win_kernel_name(32, 4, stash=False) + "(blco::KParams)"
+    probe = "k_atomic_probe(float*, long, unsigned int const*, long, int)"
+    fetch, write, atom, out = (tmp_path / x for x in ("f.csv", "w.csv", "a.csv", "c.txt"))
     # two MTTKRP dispatches (mean 300 KiB fetched), a small copy and the 1 MiB
     # calibration copy that the counter reports as 512 KiB fetched, 1024 written
-    write_csv(fetch, [(k + "(blco::KParams)", "FETCH_SIZE", 200.0),
-                      (k + "(blco::KParams)", "FETCH_SIZE", 400.0),
+    write_csv(fetch, [(k, "FETCH_SIZE", 200.0), (k, "FETCH_SIZE", 400.0),
                       ("copyBuffer small", "FETCH_SIZE", 3.0),
-                      ("copyBuffer big", "FETCH_SIZE", 512.0),
-                      ("other", "FETCH_SIZE", 1e9)])
-    write_csv(write, [(k + "(blco::KParams)", "WRITE_SIZE", 100.0),
-                      (k + "(blco::KParams)", "WRITE_SIZE", 100.0),
+                      ("copyBuffer big", "FETCH_SIZE", 512.0)])
+    write_csv(write, [(k, "WRITE_SIZE", 100.0), (k, "WRITE_SIZE", 100.0),
                       ("copyBuffer big", "WRITE_SIZE", 1024.0)])
-    bench.summarize_pmc(str(fetch), str(write), 1 << 20, out=str(out))
-    vals = dict(line.split(": ") for line in out.read_text().splitlines() if not line.startswith("#"))
-    assert vals["mttkrp_dispatches"] == "2"
-    assert float(vals["fetch_scale"]) == pytest.approx(2.0)
-    assert float(vals["write_scale"]) == pytest.approx(1.0)
-    assert float(vals["hbm_fetch_bytes_per_launch"]) == pytest.approx(300 * 1024 * 2)
-    assert float(vals["hbm_write_bytes_per_launch"]) == pytest.approx(100 * 1024)
-    assert vals["kernel_source_sha256_16"] == bench.kernel_source_hash()
+    # the probe makes 1000 row-ops and the counter reads 2 requests per row-op
+    write_csv(atom, [(k, "TCC_EA0_ATOMIC_sum", 500.0), (probe, "TCC_EA0_ATOMIC_sum", 2000.0)])
+    bench.summarize_counters(str(out), "test", str(fetch), str(write), str(atom),
+                             copy_bytes=1 << 20, probe_row_ops=1000, commands=["cmd a"])
+    c = bench.read_counters(str(out))
+    assert c is not None
+    head, per = c
+    assert per[k]["FETCH_SIZE"] == pytest.approx(300.0)
+    name = bench.win_kernel_name(32, 4, stash=False)
+    tr = bench.counter_traffic(c, name)
+    assert tr["fetch_scale"] == pytest.approx(2.0) and tr["write_scale"] == pytest.approx(1.0)
+    assert tr["bytes"] == pytest.approx(300 * 1024 * 2 + 100 * 1024)
+    ro = bench.counter_row_ops(c, name)
+    assert ro["requests_per_row_op"] == pytest.approx(2.0)
+    assert ro["row_ops"] == pytest.approx(250.0)
+    assert bench.counter_traffic(c, "k_other") is None
 
 
-def test_counter_summary_per_nonzero(bench, tmp_path):
-    k = bench.win_kernel_name(32, 3)
-    a, b, out = tmp_path / "a.csv", tmp_path / "b.csv", tmp_path / "c.txt"
-    write_csv(a, [("void " + k + "(blco::KParams)", "SQ_INSTS_VALU", 800.0),
-                  ("void " + k + "(blco::KParams)", "SQ_INSTS_VALU", 1200.0),
-                  ("void k_other(blco::KParams)", "SQ_INSTS_VALU", 5.0)])
-    write_csv(b, [("void " + k + "(blco::KParams)", "TCC_EA0_ATOMIC_sum", 58.0)])
-    bench.summarize_counters("zipf3", k, 100, str(out), str(a), str(b))
-    rows = {ln.split()[0]: ln.split()[1:] for ln in out.read_text().splitlines()
-            if ln and not ln.startswith("#") and ":" not in ln and not ln.startswith("counter")}
-    assert rows["SQ_INSTS_VALU"] == ["2", "1000.0", "10.0000"]
-    assert rows["TCC_EA0_ATOMIC_sum"] == ["1", "58.0", "0.5800"]
-
-
-def test_stale_traffic_is_not_reported(bench, tmp_path, monkeypatch):
+def test_stale_counters_are_not_used(bench, tmp_path):
     f = tmp_path / "t.txt"
     f.write_text(f"kernel_source_sha256_16: {bench.kernel_source_hash()}\n"
-                 "hbm_bytes_per_launch: 1234\n")
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.measured_traffic() == 1234.0
-    f.write_text("kernel_source_sha256_16: 0000000000000000\nhbm_bytes_per_launch: 1234\n")
-    assert bench.measured_traffic() is None
+                 "calibration_copy_bytes: 1\nprobe_row_ops: 1\nk | FETCH_SIZE | 1 | 5.0\n")
+    assert bench.read_counters(str(f)) is not None
+    f.write_text("kernel_source_sha256_16: 0000000000000000\nk | FETCH_SIZE | 1 | 5.0\n")
+    assert bench.read_counters(str(f)) is None
+
+
+def test_big_factor_rule(bench):
+    # 2^24 x 64 fp32 = 4 GiB: the other modes gather it with 64-bit addresses
+    dims = (1 << 24, 1 << 22, 1 << 20, 1 << 10)
+    assert [bench.big_factors(dims, 64, 4, n) for n in range(4)] == [False, True, True, True]
+    assert not any(bench.big_factors(dims, 32, 4, n) for n in range(4))
+    assert not any(bench.big_factors(dims, 64, 2, n) for n in range(4))

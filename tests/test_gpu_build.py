@@ -1,7 +1,8 @@
-"""BLCO construction on the GPU (blco_build_device) against the host builder,
-bit for bit: keys, values in BLCO order, block keys and block starts, the
-bit map, per-mode frequent-row counts, and MTTKRP results.  The host builder
-itself is pinned to the oracle encoder in test_host_builder.
+"""BLCO construction on the GPU (blco_build_device) against the oracle encoder
+(oracle.encode, numpy) on the same inputs, bit for bit: keys, values in BLCO
+order, block keys, block starts and the bit map.  It is also compared with the
+host builder (the frequent-row counts, which the oracle does not define, and
+MTTKRP results).
 """
 import sys
 
@@ -15,6 +16,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import oracle  # noqa: E402
+from oracle import encode as E  # noqa: E402
 import paper_2201_12523_amd as blco  # noqa: E402
 import synth  # noqa: E402
 
@@ -27,12 +29,19 @@ def say(msg):
 
 
 def same(coords, vals, dims, **kw):
-    th = blco.build(coords, vals, dims, placement="host", **kw)
     tg = blco.build_device(coords, vals, dims, **kw)
-    a, b = th.export(), tg.export()
-    for x, y, name in zip(a, b, ("keys", "values", "block ids", "block starts")):
-        np.testing.assert_array_equal(x, y, err_msg=name)
-    ih, ig = th.info(), tg.info()
+    b = tg.export()
+    ref = E.encode(coords, vals, dims, key_bits=kw.get("key_bits", 64),
+                   max_block_nnz=kw.get("max_block_nnz", 1 << 27))
+    for x, name in zip(b, ("keys", "values", "block_ids", "block_starts")):
+        np.testing.assert_array_equal(x, ref[name], err_msg=f"GPU builder vs oracle: {name}")
+    lay, ig = ref["layout"], tg.info()
+    assert (ig["total_bits"], ig["key_bits"], ig["block_bits"]) == (lay["T"], lay["K"], lay["S"])
+    assert ig["bits"] == lay["b"] and ig["kept"] == lay["w"]
+    assert ig["shift"] == lay["s"] and ig["high"] == lay["h"]
+    assert ig["nblocks"] == len(ref["block_ids"])
+    th = blco.build(coords, vals, dims, placement="host", **kw)
+    ih = th.info()
     for k in ("total_bits", "key_bits", "block_bits", "bits", "kept", "shift", "high", "nblocks",
               "nruns", "hot_rows"):
         assert ih[k] == ig[k], k
@@ -44,7 +53,7 @@ def rand_coords(rng, dims, nnz):
 
 
 @pytest.mark.parametrize("key_bits,cap", [(64, 1 << 27), (9, 100), (14, 1)])
-def test_matches_host_builder(key_bits, cap):
+def test_matches_oracle_encoder(key_bits, cap):
     rng = np.random.default_rng(key_bits)
     dims = (1000, 300, 77, 6)
     coords = rand_coords(rng, dims, 20_000)
@@ -56,11 +65,12 @@ def test_matches_host_builder(key_bits, cap):
     same(coords, vals, dims, key_bits=key_bits, max_block_nnz=cap)
 
 
-def test_index_over_64_bits():
-    # 2^24 x 2^22 x 2^20 x 2^10: 76 bits, blocks on the top 12
+@pytest.mark.parametrize("key_bits,cap", [(64, 1 << 27), (40, 1 << 27), (64, 1000)])
+def test_index_over_64_bits(key_bits, cap):
+    # 2^24 x 2^22 x 2^20 x 2^10: 76 bits, blocks on the top 12 (36 at 40 key bits)
     w = synth.WORKLOADS["zipf4"]
     coords, vals = synth.workload_tensor(w, nnz=2_000_000)
-    t = same(coords, vals, w.dims)
+    t = same(coords, vals, w.dims, key_bits=key_bits, max_block_nnz=cap)
     assert t.info()["total_bits"] == 76 and t.info()["nruns"] > 1
 
 
@@ -111,8 +121,9 @@ def test_errors_and_pinned_placement():
         blco.build_device(coords, vals, dims, placement="host")
     tp = blco.build_device(coords, vals, dims, placement="pinned")
     th = blco.build(coords, vals, dims, placement="host")
-    for x, y in zip(tp.export(), th.export()):
-        np.testing.assert_array_equal(x, y)
+    ref = E.encode(coords, vals, dims)
+    for x, name in zip(tp.export(), ("keys", "values", "block_ids", "block_starts")):
+        np.testing.assert_array_equal(x, ref[name], err_msg=name)
     A = [rng.standard_normal((d, 8)).astype(np.float32) for d in dims]
     F = [torch.from_numpy(a).to(DEV) for a in A]
     out = blco.mttkrp_stream(tp, 1, F, device_budget=1 << 30)

@@ -372,6 +372,21 @@ def test_empty_tensor_zero_fills():
     assert float(out.abs().sum()) == 0.0
 
 
+def test_empty_tensor_loss_is_zero():
+    """No non-zeros: loss 0 and no factor row read; NULL factors are still rejected."""
+    t = blco.build([np.zeros(0, np.uint32)] * 3, np.zeros(0, np.float32), (4, 5, 6))
+    F = _dev_factors([np.ones((d, 3), np.float32) for d in (4, 5, 6)])
+    loss = torch.full((), 7.0, dtype=torch.float64, device=DEV)
+    blco.sampled_loss(t, F, residual=torch.empty(1, device=DEV), loss=loss)
+    torch.cuda.synchronize()
+    assert float(loss) == 0.0
+    import ctypes
+    arr = (ctypes.c_void_p * 3)(F[0].data_ptr(), None, F[2].data_ptr())
+    L = blco.lib()
+    assert L.blco_sampled_loss(t.handle, arr, 0, 3, None, loss.data_ptr(), None) == -1
+    assert b"factors[1]" in L.blco_last_error()
+
+
 @pytest.mark.skipif(os.environ.get("BLCO_SKIP_FULL") == "1", reason="full-size case disabled")
 def test_zipf3_full_size_sampled_rows():
     """The 2^22 x 2^21 x 2^20, 50M-non-zero Zipf(1.1) workload at full size, R = 32,

@@ -199,3 +199,63 @@ def test_rows_f32_variant_matches_fp64():
         M2, S2 = oracle.mttkrp_rows_f32(coords, vals32, A32, n, rows, dims)
         np.testing.assert_array_equal(M, M2)
         np.testing.assert_array_equal(S, S2)
+
+
+@pytest.mark.parametrize("threads,force_atomic", [(1, False), (3, False), (8, False), (5, True)])
+def test_omp_oracle_matches_serial(threads, force_atomic):
+    """The multi-threaded oracle (used to time the oracle on all host cores) changes only
+    the order of the additions: equal to the serial oracle within fp64 rounding, and
+    pinned independently by the dense brute force of Eq. (1)."""
+    dims = (37, 11, 23)
+    coords, vals = _rand_sparse(dims, 4000, 31 + threads, dup=True)
+    rng = np.random.default_rng(9)
+    A = [rng.standard_normal((d, 6)) for d in dims]
+    X = _dense(coords, vals, dims)
+    for n in range(3):
+        M, S = oracle.mttkrp(coords, vals, A, n)
+        Mo, So, used, atomic = oracle.mttkrp_omp(coords, vals, A, n, threads=threads,
+                                                 force_atomic=force_atomic)
+        assert used == threads and atomic == force_atomic
+        assert np.all(np.abs(Mo - M) <= 1e-12 * S)
+        assert np.allclose(So, S, rtol=1e-12, atol=0)
+        brute = _unfold(X, n) @ _khatri_rao_eq1(A, n)
+        assert np.allclose(Mo, brute, rtol=1e-10, atol=1e-10)
+
+
+def test_omp_oracle_fewer_nonzeros_than_threads():
+    dims = (4, 5)
+    coords, vals = _rand_sparse(dims, 3, 2)
+    A = [np.ones((d, 2)) for d in dims]
+    M, S = oracle.mttkrp(coords, vals, A, 0)
+    Mo, So, used, _ = oracle.mttkrp_omp(coords, vals, A, 0, threads=8)
+    assert used == 8
+    assert np.array_equal(M, Mo) and np.array_equal(S, So)
+    # all-ones factors: slice sums
+    assert np.allclose(Mo[:, 0], np.bincount(coords[0], weights=vals, minlength=4))
+
+
+@pytest.mark.parametrize("threads", [1, 4, 7])
+def test_omp_rows_oracle_matches_serial(threads):
+    """The threaded row-restricted oracle (fp64 values, fp32 factors widened as read) equals
+    the serial row oracles within fp64 rounding; the serial ones are pinned above."""
+    dims = (50, 13, 29, 4)
+    coords, vals = _rand_sparse(dims, 6000, 71 + threads, dup=True)
+    rng = np.random.default_rng(3)
+    A = [rng.standard_normal((d, 5)).astype(np.float32) for d in dims]
+    for n in range(4):
+        rows = np.unique(rng.integers(0, dims[n], 9)).astype(np.uint32)
+        M, S = oracle.mttkrp_rows(coords, vals, [a.astype(np.float64) for a in A], n, rows, dims)
+        Mo, So = oracle.mttkrp_rows_omp(coords, vals, A, n, rows, dims, threads=threads)
+        assert np.all(np.abs(Mo - M) <= 1e-12 * S) and np.allclose(So, S, rtol=1e-12, atol=0)
+        Mf, Sf = oracle.mttkrp_rows_f32(coords, vals.astype(np.float32), A, n, rows, dims)
+        Mo2, So2 = oracle.mttkrp_rows_omp(coords, vals.astype(np.float32), A, n, rows, dims,
+                                          threads=threads)
+        assert np.all(np.abs(Mo2 - Mf) <= 1e-12 * Sf)
+
+
+def test_omp_cp_model_bit_identical():
+    dims = (30, 20, 10)
+    coords, _ = _rand_sparse(dims, 5000, 5)
+    rng = np.random.default_rng(8)
+    A = [rng.standard_normal((d, 7)) for d in dims]
+    assert np.array_equal(oracle.cp_model(coords, A), oracle.cp_model_omp(coords, A, threads=5))
