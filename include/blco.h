@@ -217,6 +217,44 @@ int blco_sampled_loss(blco_tensor* t, const void* const* factors, int factor_dty
                       float* residual, double* loss, void* stream);
 
 /*
+ * Sparse CP fit loss and its gradient with respect to every factor in one call
+ * (model of Section 2.2; the gradient of 1/2 sum_k e_k^2 with respect to A^(m)
+ * is -MTTKRP_m(E), E the tensor of residuals e_k = x_k - xhat_k at the
+ * non-zeros, since d xhat_k / d A^(m)[i, r] = prod_{j != m} A^(j)[i_j^k, r]):
+ *   *loss    = 1/2 sum_k e_k^2  (fp64, fixed summation order)
+ *   grads[m] = -alpha * (scale ? *scale : 1) * MTTKRP_m(E)  for every mode m
+ * grads: host array of N device pointers, I_m x R fp32 each, overwritten, not
+ * overlapping.  factors: all N non-NULL.  The residual is formed inside the
+ * MTTKRP walk of one mode (the first whose register-based kernel takes R <= 64
+ * with 32-bit gather offsets), which also gathers the target row, so no
+ * separate pass over the non-zeros computes the model; the other modes' MTTKRPs
+ * read that residual.  (When no mode qualifies, the sampled-loss kernel forms
+ * the residual first.)
+ * DEVICE placement: residual (device, nnz fp32) receives e in BLCO order;
+ *   device_budget_bytes is not used.
+ * PINNED placement: residual must be NULL; the non-zeros are streamed as in
+ *   blco_mttkrp_stream_all, each chunk crossing the host link once for the loss
+ *   and all N gradients; the budget covers the tensor's tables, every factor,
+ *   every gradient and two staging buffers of 16 bytes per non-zero (key,
+ *   value, residual).
+ * Products are fp32 (factors fp32 or bf16); the result equals blco_sampled_loss
+ * followed by blco_mttkrp_v of its residual in every mode, up to rounding.
+ * Uses buffers held by the tensor (no concurrent call on the same tensor).
+ * Errors: EINVAL (null pointers, rank, dtype, placement, overlapping grads),
+ * ENOMEM (budget), EUNSUPPORTED (a forced hierarchical mode too long).
+ */
+int blco_cp_grad(blco_tensor* t, const void* const* factors, int factor_dtype, int rank,
+                 const double* scale, double alpha, float* residual, double* loss,
+                 float* const* grads, size_t device_budget_bytes, void* stream);
+
+/*
+ * x[i] *= alpha * (scale ? *scale : 1) for i < n (x device fp32, scale a device
+ * double or NULL): the chain-rule factor of an autograd backward applied to
+ * gradients computed ahead by blco_cp_grad.  Errors: EINVAL.
+ */
+int blco_scale(float* x, int64_t n, const double* scale, double alpha, void* stream);
+
+/*
  * Choose the conflict-resolution mechanism of every later MTTKRP call on t
  * (blco_mttkrp*, blco_mttkrp_stream*, the CP gradient), Sections 5.1-5.3:
  *   BLCO_RES_REGISTER: each window of non-zeros is sorted by target row and

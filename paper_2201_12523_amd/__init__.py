@@ -18,7 +18,7 @@ import numpy as np
 import torch  # noqa: F401  (must precede loading libblco.so)
 
 __all__ = ["BLCOTensor", "build", "mttkrp", "mttkrp_acc", "mttkrp_v", "mttkrp_stream",
-           "mttkrp_stream_all", "sampled_loss",
+           "mttkrp_stream_all", "sampled_loss", "cp_grad",
            "cast_bf16", "atomic_probe", "CPLoss", "BLCOError", "lib", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -32,7 +32,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: 
 
 EXPORTED = ["blco_build", "blco_mttkrp", "blco_mttkrp_acc", "blco_mttkrp_v", "blco_mttkrp_stream",
             "blco_mttkrp_stream_all",
-            "blco_sampled_loss", "blco_cast_bf16", "blco_set_resolution", "blco_resolution",
+            "blco_sampled_loss", "blco_cp_grad", "blco_scale", "blco_cast_bf16", "blco_set_resolution", "blco_resolution",
             "blco_gram", "blco_cp_als", "blco_build_device",
             "blco_atomic_probe", "blco_frequent_rows", "blco_info", "blco_export", "blco_free",
             "blco_last_error"]
@@ -92,6 +92,9 @@ def lib():
         L.blco_mttkrp_stream_all.argtypes = [p, p, i32, i32, p, ctypes.c_size_t, p]
         L.blco_sampled_loss.argtypes = [p, p, i32, i32, p, p, p]
         L.blco_cast_bf16.argtypes = [p, p, i64, p]
+        L.blco_cp_grad.argtypes = [p, p, i32, i32, p, ctypes.c_double, p, p, p, ctypes.c_size_t,
+                                   p]
+        L.blco_scale.argtypes = [p, i64, p, ctypes.c_double, p]
         L.blco_info.argtypes = [p, ctypes.POINTER(_Info)]
         L.blco_export.argtypes = [p, p, p, p, p]
         L.blco_set_resolution.argtypes = [p, i32]
@@ -375,6 +378,47 @@ def sampled_loss(t, factors, residual=None, loss=None, stream=None):
     return loss, residual
 
 
+def cp_grad(t, factors, grads=None, residual=None, loss=None, scale=None, alpha=1.0,
+            device_budget=8_000_000_000, stream=None):
+    """(loss, grads, residual): the sparse CP fit loss 1/2 sum_k e_k^2 (float64 device scalar)
+    and alpha * scale * dloss/dA^(m) = -alpha * scale * MTTKRP_m(E) for every mode, in one call.
+
+    A device tensor also returns the residual e (BLCO order); a tensor in pinned host
+    memory is streamed under `device_budget` (residual None)."""
+    arr, dt, R, _keep = _factor_args(t, factors, None)
+    dev = _device_of(factors)
+    N = len(t.dims)
+    if grads is None:
+        grads = [None] * N
+    grads = [_out(t, m, R, grads[m], dev) for m in range(N)]
+    pinned = t.info()["placement"] == PLACEMENTS["pinned"]
+    if not pinned and residual is None:
+        residual = torch.empty(max(t.nnz, 1), dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float64, device=dev)
+    sp = None
+    if scale is not None:
+        if scale.dtype != torch.float64 or scale.numel() != 1:
+            raise ValueError("scale must be a one-element float64 device tensor")
+        sp = scale.data_ptr()
+    ptrs = (ctypes.c_void_p * N)(*[g.data_ptr() for g in grads])
+    _check(lib().blco_cp_grad(t.handle, arr, dt, R, sp, float(alpha),
+                              None if pinned else residual.data_ptr(), loss.data_ptr(), ptrs,
+                              int(device_budget), _stream(stream)))
+    return loss, grads, (None if pinned else residual)
+
+
+def scale_(x, scale, alpha=1.0, stream=None):
+    """x *= alpha * scale (x float32 device tensor, scale a one-element float64 device tensor)."""
+    if x.dtype != torch.float32 or not x.is_contiguous():
+        raise ValueError("x must be contiguous float32")
+    if scale.dtype != torch.float64 or scale.numel() != 1:
+        raise ValueError("scale must be a one-element float64 device tensor")
+    _check(lib().blco_scale(x.data_ptr(), x.numel(), scale.data_ptr(), float(alpha),
+                            _stream(stream)))
+    return x
+
+
 def cast_bf16(x, stream=None):
     """Round-to-nearest-even bfloat16 copy of a float32 device tensor (library kernel)."""
     if x.dtype != torch.float32 or not x.is_contiguous():
@@ -433,10 +477,16 @@ class CPLoss(torch.autograd.Function):
     """Sparse CP fit loss 1/2 sum_nnz (x - sum_r prod_m A^(m))^2 with a hand-written backward.
 
     forward(t, storage, *A): A are fp32 factor masters (I_m x R); storage "fp32"
-    or "bf16" (round-to-nearest-even copies used by the kernels).  The loss is
-    a float64 device scalar.  backward: dL/dA^(n) = -g * MTTKRP_n(E), E the
-    residual tensor, one MTTKRP per mode.
+    or "bf16" (round-to-nearest-even copies used by the kernels).  The loss is a
+    float64 device scalar.  When any factor needs a gradient, the forward makes one
+    blco_cp_grad call: the loss and dL/dA^(m) = -MTTKRP_m(E) for every mode (E the
+    residual tensor), the residual formed inside one mode's MTTKRP walk; the backward
+    then only scales them by the incoming gradient g.  Otherwise the forward runs the
+    sampled-loss kernel alone.  A tensor in pinned host memory is streamed (budget:
+    CPLoss.device_budget bytes).
     """
+
+    device_budget = 8_000_000_000
 
     @staticmethod
     def forward(ctx, t, storage, *A):
@@ -446,19 +496,23 @@ class CPLoss(torch.autograd.Function):
             F = [a.contiguous() for a in A]
         else:
             raise ValueError("storage must be 'fp32' or 'bf16'")
-        loss, resid = sampled_loss(t, F)
-        ctx.t = t
-        ctx.F = F
-        ctx.save_for_backward(resid)
+        pinned = t.info()["placement"] == PLACEMENTS["pinned"]
+        if any(ctx.needs_input_grad[2:]) or pinned:
+            loss, grads, _ = cp_grad(t, F, device_budget=CPLoss.device_budget)
+            ctx.grads = grads
+        else:
+            loss, _ = sampled_loss(t, F)
+            ctx.grads = None
         return loss
 
     @staticmethod
     def backward(ctx, g):
-        (resid,) = ctx.saved_tensors
         g = g.detach().reshape(1)
         if g.dtype != torch.float64:
             raise ValueError("loss gradient must be float64")
         g = g.contiguous()
-        grads = [mttkrp_v(ctx.t, n, resid, ctx.F, scale=g, alpha=-1.0)
-                 for n in range(len(ctx.F))]
+        grads = ctx.grads
+        ctx.grads = None
+        for x in grads:
+            scale_(x, g)
         return (None, None, *grads)

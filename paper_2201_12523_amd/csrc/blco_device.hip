@@ -259,7 +259,13 @@ __device__ __forceinline__ int hot_lookup(const uint32_t* keys, const uint32_t* 
 // own, so each has exactly one segment per window, and its flush is a plain
 // add into the workgroup's LDS stash row; the stash goes to the output with
 // one atomic per (row, rank) when the workgroup ends.
-template <int LPN, int RPL, typename FT, int N, bool BIG, bool STASH>
+//
+// RES (the fused CP-gradient walk, one rank slice): the values are the data x_k,
+// and each position also gathers its target row, so the walk forms the model
+// xhat_k = sum_r prod_m A^(m)[i_m^k, r] (a sum over the 16 lanes of the group),
+// the residual e_k = x_k - xhat_k, which it writes to p.resid in BLCO order, and
+// sums e_k * prod_{m != mode} A^(m) instead of x_k * prod_{m != mode} A^(m).
+template <int LPN, int RPL, typename FT, int N, bool BIG, bool STASH, bool RES = false>
 __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   constexpr int G = kWin / LPN;                 // groups of LPN lanes
   constexpr int PPG = kWin / G;                 // grouped positions per group (= LPN)
@@ -268,8 +274,11 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   // the registers from spilling and measured 8% and 3% faster
   constexpr int UW = (N == 3 && RPL == 1) ? 4 : (N == 3 && RPL == 4) ? 1 : BLCO_WIN_U / RPL;
   constexpr int U = PPG < UW ? PPG : UW;
-  constexpr int NF = N + 1;                     // record fields
+  // record fields: the other modes' row offsets, target, value; with RES also
+  // the target row's offset and the position in the window
+  constexpr int NF = RES ? N + 3 : N + 1;
   constexpr int NP = NF <= 4 ? 4 : ((NF + 1) / 2) * 2;
+  static_assert(!RES || (LPN == 16 && !BIG), "fused residual walk: 16-lane groups, 32-bit offsets");
   __shared__ __align__(16) uint32_t s_rec[kWin * NP];  // records by grouped position
   __shared__ uint64_t s_end[kWin / 64];
   // the histogram (processing) and the carry partial sums (computing) are never
@@ -326,6 +335,10 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
     rs[j] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.A[m]), 0, (int)p.abytes[m],
                                               (int)kBufFlags);
   }
+  // the target mode's factor (read by the fused residual walk only)
+  const __amdgpu_buffer_rsrc_t rs_t = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(p.A[RES ? p.mode : 0]), 0, RES ? (int)p.abytes[p.mode] : 0,
+      (int)kBufFlags);
   const float scale = term_scale(p);
   const int g = tid / LPN;
   const int rl = tid % LPN;
@@ -380,6 +393,10 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
     }
     s_rec[pos * NP + N - 1] = tfield;
     s_rec[pos * NP + N] = __float_as_uint(x);
+    if constexpr (RES) {
+      s_rec[pos * NP + N + 1] = tgt * p.rowbytes;
+      s_rec[pos * NP + N + 2] = (uint32_t)tid;
+    }
     __syncthreads();
     {
       const uint32_t t0 = s_rec[tid * NP + N - 1];
@@ -429,6 +446,9 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
       bool first = true, has_carry = false;
       for (int q0 = 0; q0 < PPG; q0 += U) {
         float pr[U][RPL];
+        float ta[RES ? U : 1][RPL];
+        float xs[RES ? U : 1];
+        uint32_t wpos[RES ? U : 1];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           // the record of position q0 + u: from the row, or from LDS
@@ -441,7 +461,14 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
           const uint32_t* er = &s_rec[(p0 + q0 + u) * NP];
           const float xv = __uint_as_float(kRowB ? e[N] : er[N]);
 #pragma unroll
-          for (int k = 0; k < RPL; ++k) pr[u][k] = xv;
+          for (int k = 0; k < RPL; ++k) pr[u][k] = RES ? 1.f : xv;
+          if constexpr (RES) {
+            xs[u] = xv;
+            const uint32_t toff = kRowB ? e[N + 1] : er[N + 1];
+            wpos[u] = kRowB ? e[N + 2] : er[N + 2];
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) ta[u][k] = ld_buf<FT>(rs_t, toff + loff[k]);
+          }
 #pragma unroll
           for (int j = 0; j + 1 < N; ++j) {
             const uint32_t f = kRowB ? e[j] : er[j];
@@ -454,6 +481,23 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
 #pragma unroll
               for (int k = 0; k < RPL; ++k) pr[u][k] *= ld_buf<FT>(rs[j], f + loff[k]);
             }
+          }
+        }
+        if constexpr (RES) {
+          // model at each position (sum over the group's 16 lanes), residual, and
+          // the residual-scaled product of the other modes' rows
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            float part = 0.f;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k)
+              if (ract[k]) part += pr[u][k] * ta[u][k];
+#pragma unroll
+            for (int off = LPN / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+            const float ev = xs[u] - part;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) pr[u][k] *= ev;
+            if (rl == 0 && (int)wpos[u] < nvalid) p.resid[k0 + wpos[u]] = ev;
           }
         }
 #pragma unroll
@@ -848,6 +892,28 @@ __global__ __launch_bounds__(kBlock) void k_loss_tile(KParams p) {
   }
 }
 
+// Sum of squares of a residual in fp64: workgroup b sums entries
+// [b * kSqPer, (b + 1) * kSqPer) in a fixed order into part[b].
+constexpr int kSqPer = 4096;
+__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ r, int64_t n,
+                                               double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int64_t lo = (int64_t)blockIdx.x * kSqPer;
+  const int64_t hi = min(n, lo + (int64_t)kSqPer);
+  double a = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    const double e = (double)r[i];
+    a += e * e;
+  }
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 // loss = 1/2 * sum of the partials, in a fixed order (one workgroup).
 __global__ __launch_bounds__(1024) void k_reduce_loss(const double* __restrict__ part, int64_t n,
                                                       double* __restrict__ loss) {
@@ -896,6 +962,14 @@ __global__ __launch_bounds__(256) void k_atomic_probe(float* __restrict__ out, i
   for (int r = rl; r < R; r += 16) unsafeAtomicAdd(dst + r, 1.0f);
 }
 
+// x[i] *= (float)(alpha * scale[0]) (the chain-rule factor of an autograd backward).
+__global__ __launch_bounds__(256) void k_scale(float* __restrict__ x, int64_t n,
+                                               const double* __restrict__ scale, double alpha) {
+  const float f = (float)(alpha * (scale ? scale[0] : 1.0));
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) x[i] *= f;
+}
+
 // ====================================================================== dispatch
 
 typedef void (*KernelFn)(KParams);
@@ -917,6 +991,32 @@ static KernelFn pick_win_s(int N) {
 template <int LPN, int RPL, typename FT, bool BIG>
 static KernelFn pick_win(int N, bool stash) {
   return stash ? pick_win_s<LPN, RPL, FT, BIG, true>(N) : pick_win_s<LPN, RPL, FT, BIG, false>(N);
+}
+
+// the fused residual walk (16-lane groups, one rank slice of at most 64, 32-bit offsets)
+template <int RPL, typename FT, bool STASH>
+static KernelFn pick_res_s(int N) {
+  switch (N) {
+    case 1: return k_mttkrp_win<16, RPL, FT, 1, false, STASH, true>;
+    case 2: return k_mttkrp_win<16, RPL, FT, 2, false, STASH, true>;
+    case 3: return k_mttkrp_win<16, RPL, FT, 3, false, STASH, true>;
+    case 4: return k_mttkrp_win<16, RPL, FT, 4, false, STASH, true>;
+    case 5: return k_mttkrp_win<16, RPL, FT, 5, false, STASH, true>;
+    case 6: return k_mttkrp_win<16, RPL, FT, 6, false, STASH, true>;
+    case 7: return k_mttkrp_win<16, RPL, FT, 7, false, STASH, true>;
+    default: return k_mttkrp_win<16, RPL, FT, 8, false, STASH, true>;
+  }
+}
+
+template <typename FT>
+static KernelFn select_res_t(int N, int R, bool stash) {
+  if (R <= 16) return stash ? pick_res_s<1, FT, true>(N) : pick_res_s<1, FT, false>(N);
+  if (R <= 32) return stash ? pick_res_s<2, FT, true>(N) : pick_res_s<2, FT, false>(N);
+  return stash ? pick_res_s<4, FT, true>(N) : pick_res_s<4, FT, false>(N);
+}
+
+static KernelFn select_res(int N, int R, int fdt, bool stash) {
+  return fdt == BLCO_F32 ? select_res_t<float>(N, R, stash) : select_res_t<uint16_t>(N, R, stash);
 }
 
 typedef void (*ShortFn)(KParams, int64_t);
@@ -1148,10 +1248,12 @@ static int stash_rows(const blco_tensor* t, int mode, int rank, KernelFn f) {
 }
 
 // Launch the MTTKRP kernel over [lo, lo + n) of the tensor given by keys/vals.
+// With resid != nullptr the fused residual walk runs instead (the caller has
+// checked fused_mode_ok): resid[0, n) receives the residual of each non-zero.
 static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float* vals,
                          int64_t lo, int64_t n, int mode, const void* const* factors, int fdt,
                          int rank, float scale, const double* scale_dev, float* out,
-                         hipStream_t s) {
+                         hipStream_t s, float* resid = nullptr) {
   if (n <= 0) return BLCO_OK;
   KParams p;
   fill_params(t, &p);
@@ -1178,6 +1280,10 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
   int sw = 0;
   const int res = resolve(t, mode, rank, &sw);
   if (res < 0) return res;
+  if (resid && (res != BLCO_RES_REGISTER || big || rank > 64 ||
+                (size_t)t->lay.dims[mode] * rank * fsz > 0xFFFFFFFFull))
+    return set_error(BLCO_EUNSUPPORTED, "fused residual walk on mode %d", mode);
+  p.resid = resid;
   if (res == BLCO_RES_HIERARCHICAL) {
     p.short_rows = (uint32_t)t->lay.dims[mode];
     p.short_width = sw;
@@ -1194,12 +1300,13 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
     return BLCO_OK;
   }
   {
-    KernelFn f = select_win(t->lay.N, rank, fdt, big, true);
+    const int N = t->lay.N;
+    KernelFn f = resid ? select_res(N, rank, fdt, true) : select_win(N, rank, fdt, big, true);
     const int64_t nwin = (n + kWin - 1) / kWin;
     const int K = stash_rows(t, mode, rank, f);
     p.hot = t->d_hot + (size_t)mode * kHotMax;
     p.nhot = K;
-    if (K == 0) f = select_win(t->lay.N, rank, fdt, big, false);
+    if (K == 0) f = resid ? select_res(N, rank, fdt, false) : select_win(N, rank, fdt, big, false);
     const size_t dyn = K > 0 ? (size_t)K * rank * 4 + 2 * (size_t)kHotSlots * 4 : 0;
     // with a stash: persistent workgroups, kWinRounds times the resident count
     // (two per CU), which balances the end of the launch (measured 1-2% faster
@@ -1245,6 +1352,7 @@ static void release_device(blco_tensor* t) {
   for (int i = 0; i < 2; ++i) {
     if (st.d_keys[i]) (void)hipFree(st.d_keys[i]);
     if (st.d_vals[i]) (void)hipFree(st.d_vals[i]);
+    if (st.d_res[i]) (void)hipFree(st.d_res[i]);
     if (st.ev_ready[i]) (void)hipEventDestroy((hipEvent_t)st.ev_ready[i]);
     if (st.ev_free[i]) (void)hipEventDestroy((hipEvent_t)st.ev_free[i]);
   }
@@ -1377,8 +1485,122 @@ extern "C" int blco_mttkrp_acc(blco_tensor* t, int mode, const void* const* fact
 // for every chunk, run the MTTKRP of each selected mode (outs[m] != NULL) while
 // the chunk is resident.  Device bytes: factors read + selected outputs +
 // tensor tables + two staging buffers <= budget.
+// Whether the fused residual walk can serve mode m: register-based resolution,
+// one rank slice of 16-lane groups (R <= 64) and 32-bit gather offsets.
+static bool fused_mode_ok(const blco_tensor* t, int m, int rank, int fdt) {
+  int sw = 0;
+  if (resolve(t, m, rank, &sw) != BLCO_RES_REGISTER) {
+    clear_error();
+    return false;
+  }
+  const size_t fsz = factor_elem_bytes(fdt);
+  if (rank > 64 || (size_t)rank * fsz >= (1ULL << 31)) return false;
+  for (int j = 0; j < t->lay.N; ++j)
+    if ((size_t)t->lay.dims[j] * rank * fsz > 0xFFFFFFFFull) return false;
+  return true;
+}
+
+// Partial sums the loss needs per launch of the sampled-loss kernel over n non-zeros.
+static int64_t loss_blocks(int64_t n) { return ((n + 63) / 64 + kWaves - 1) / kWaves; }
+
+// The sampled-loss kernel over [lo, lo + n) of the tensor given by keys/vals: the
+// residual of each non-zero into resid (may be NULL) and one fp64 partial sum of
+// squared residuals per workgroup into partials[0, loss_blocks(n)).
+static int launch_loss(const blco_tensor* t, const uint64_t* keys, const float* vals, int64_t lo,
+                       int64_t n, const void* const* factors, int fdt, int rank, float* resid,
+                       double* partials, hipStream_t s) {
+  if (n <= 0) return BLCO_OK;
+  KParams p;
+  fill_params(t, &p);
+  p.keys = keys;
+  p.vals = vals;
+  p.base = lo;
+  p.n = n;
+  for (int m = 0; m < t->lay.N; ++m) p.A[m] = factors[m];
+  p.out = resid;
+  p.partials = partials;
+  p.R = rank;
+  p.mode = -1;
+  // factors below 4 GiB are gathered with 32-bit byte offsets, larger ones
+  // with 64-bit addresses
+  const size_t fsz = factor_elem_bytes(fdt);
+  p.rowbytes = (uint32_t)((size_t)rank * fsz);
+  bool big = (size_t)rank * fsz >= (1ULL << 31);
+  for (int m = 0; m < t->lay.N; ++m) {
+    const size_t bytes = (size_t)t->lay.dims[m] * rank * fsz;
+    p.abytes[m] = (uint32_t)std::min<size_t>(bytes, 0xFFFFFFFFull);
+    if (bytes > 0xFFFFFFFFull) big = true;
+  }
+  KernelFn f = select_loss(t->lay.N, rank, fdt, big);
+  hipLaunchKernelGGL(f, dim3((unsigned)loss_blocks(n)), dim3(kBlock), 0, s, p);
+  HIPCHK(hipGetLastError());
+  return BLCO_OK;
+}
+
+// Device array of at least `count` fp64 partial sums held by the tensor.
+static int ensure_partials(blco_tensor* t, int64_t count, hipStream_t s) {
+  count = std::max<int64_t>(count, 1);
+  if (t->partials_cap >= count) return BLCO_OK;
+  if (t->d_partials) {
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipFree(t->d_partials));
+    t->d_partials = nullptr;
+    t->partials_cap = 0;
+  }
+  HIPCHK(hipMalloc((void**)&t->d_partials, sizeof(double) * (size_t)count));
+  t->partials_cap = count;
+  return BLCO_OK;
+}
+
+// The CP gradient of blco_cp_grad inside stream_modes: the residual comes from the
+// fused walk of mode m0 (or, when no mode allows it, from the sampled-loss kernel)
+// and feeds the other modes' MTTKRPs.
+struct GradArgs {
+  int m0;                   // mode of the fused residual walk, -1: sampled-loss kernel first
+  float scale;              // host-side scale of every gradient term (-alpha)
+  const double* scale_dev;  // optional device-side scale
+  float* resid;             // DEVICE placement: the caller's residual (nnz)
+  double* loss;             // device: 1/2 sum of squared residuals
+};
+
+// Residual and gradients of one range [lo, lo + n) whose keys/vals are given;
+// partial sums of squared residuals go to part[0, ...) and their count to *nparts.
+static int grad_range(blco_tensor* t, const GradArgs& g, const uint64_t* keys, const float* vals,
+                      int64_t lo, int64_t n, const void* const* factors, int fdt, int rank,
+                      float* const* outs, float* resid, double* part, int64_t* nparts,
+                      hipStream_t s) {
+  int rc;
+  *nparts = 0;
+  if (n <= 0) return BLCO_OK;
+  if (g.m0 >= 0) {
+    if ((rc = launch_mttkrp(t, keys, vals, lo, n, g.m0, factors, fdt, rank, g.scale, g.scale_dev,
+                            outs[g.m0], s, resid)))
+      return rc;
+    *nparts = (n + kSqPer - 1) / kSqPer;
+    hipLaunchKernelGGL(k_sumsq, dim3((unsigned)*nparts), dim3(256), 0, s, (const float*)resid, n,
+                       part);
+    HIPCHK(hipGetLastError());
+  } else {
+    if ((rc = launch_loss(t, keys, vals, lo, n, factors, fdt, rank, resid, part, s))) return rc;
+    *nparts = loss_blocks(n);
+  }
+  for (int m = 0; m < t->lay.N; ++m) {
+    if (m == g.m0) continue;
+    if ((rc = launch_mttkrp(t, keys, resid, lo, n, m, factors, fdt, rank, g.scale, g.scale_dev,
+                            outs[m], s)))
+      return rc;
+  }
+  return BLCO_OK;
+}
+
+// Partial sums per range of n non-zeros (the larger of the two kernels' counts).
+static int64_t grad_parts(int64_t n) {
+  return std::max<int64_t>((n + kSqPer - 1) / kSqPer, loss_blocks(n));
+}
+
 static int stream_modes(blco_tensor* t, const void* const* factors, int factor_dtype, int rank,
-                        float* const* outs, size_t device_budget_bytes, hipStream_t s) {
+                        float* const* outs, size_t device_budget_bytes, hipStream_t s,
+                        const GradArgs* grad = nullptr) {
   const Layout& L = t->lay;
   bool need[BLCO_MAX_MODES] = {};
   int nsel = 0;
@@ -1386,7 +1608,7 @@ static int stream_modes(blco_tensor* t, const void* const* factors, int factor_d
     if (outs[m]) {
       ++nsel;
       for (int j = 0; j < L.N; ++j)
-        if (j != m) need[j] = true;
+        if (j != m || grad) need[j] = true;   // the residual reads every factor
     }
   if (nsel == 0) return set_error(BLCO_EINVAL, "no output given");
   size_t fixed = t->device_bytes;
@@ -1395,6 +1617,22 @@ static int stream_modes(blco_tensor* t, const void* const* factors, int factor_d
     if (need[m]) fixed += (size_t)L.dims[m] * rank * factor_elem_bytes(factor_dtype);
   }
   int rc;
+  if (t->placement == BLCO_PLACE_DEVICE && grad) {
+    for (int m = 0; m < L.N; ++m)
+      if ((rc = fill_zero(outs[m], (int64_t)L.dims[m] * rank, s))) return rc;
+    if ((rc = ensure_partials(t, grad_parts(t->nnz), s))) return rc;
+    int64_t np = 0;
+    if ((rc = grad_range(t, *grad, t->d_keys, t->d_vals, 0, t->nnz, factors, factor_dtype, rank,
+                         outs, grad->resid, t->d_partials, &np, s)))
+      return rc;
+    hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(1024), 0, s, (const double*)t->d_partials, np,
+                       grad->loss);
+    HIPCHK(hipGetLastError());
+    t->stream_peak_bytes = fixed;
+    t->stream_chunks = 0;
+    t->st.timed_chunks = 0;
+    return BLCO_OK;
+  }
   if (t->placement == BLCO_PLACE_DEVICE) {
     if (fixed > device_budget_bytes)
       return set_error(BLCO_ENOMEM, "budget %zu below factors + outputs + tensor = %zu",
@@ -1413,7 +1651,8 @@ static int stream_modes(blco_tensor* t, const void* const* factors, int factor_d
   }
   if (t->placement != BLCO_PLACE_PINNED)
     return set_error(BLCO_EINVAL, "streaming needs a tensor in pinned host memory");
-  const size_t per_nnz = sizeof(uint64_t) + sizeof(float);
+  // staging per non-zero: key and value, and the chunk's residual for the gradient
+  const size_t per_nnz = sizeof(uint64_t) + sizeof(float) + (grad ? sizeof(float) : 0);
   if (device_budget_bytes < fixed + 2 * 64 * per_nnz)
     return set_error(BLCO_ENOMEM, "budget %zu cannot hold factors + outputs + tables (%zu) and "
                                   "two staging buffers", device_budget_bytes, fixed);
@@ -1452,9 +1691,21 @@ static int stream_modes(blco_tensor* t, const void* const* factors, int factor_d
     }
     st.cap_nnz = cap;
   }
+  if (grad && st.res_cap != cap) {
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(hipEventSynchronize((hipEvent_t)st.ev_free[i]));
+      if (st.d_res[i]) HIPCHK(hipFree(st.d_res[i]));
+      st.d_res[i] = nullptr;
+    }
+    st.res_cap = 0;
+    for (int i = 0; i < 2; ++i) HIPCHK(hipMalloc((void**)&st.d_res[i], sizeof(float) * (size_t)cap));
+    st.res_cap = cap;
+  }
   for (int m = 0; m < L.N; ++m)
     if (outs[m] && (rc = fill_zero(outs[m], (int64_t)L.dims[m] * rank, s))) return rc;
   const int64_t nchunks = (t->nnz + cap - 1) / cap;
+  if (grad && (rc = ensure_partials(t, nchunks * grad_parts(cap), s))) return rc;
+  int64_t poff = 0;   // partial sums written so far (CP gradient)
   // the previous call's timing events must have fired before they are reused
   for (size_t i = 0; i < st.ev_t.size(); ++i) HIPCHK(hipEventSynchronize((hipEvent_t)st.ev_t[i]));
   while ((int64_t)st.ev_t.size() < 4 * nchunks) {
@@ -1479,14 +1730,27 @@ static int stream_modes(blco_tensor* t, const void* const* factors, int factor_d
     HIPCHK(hipEventRecord((hipEvent_t)st.ev_ready[b], cs));
     HIPCHK(hipStreamWaitEvent(s, (hipEvent_t)st.ev_ready[b], 0));
     HIPCHK(hipEventRecord(ev[2], s));
-    for (int m = 0; m < L.N; ++m) {
-      if (!outs[m]) continue;
-      if ((rc = launch_mttkrp(t, st.d_keys[b], st.d_vals[b], lo, cnt, m, factors, factor_dtype,
-                              rank, 1.0f, nullptr, outs[m], s)))
+    if (grad) {
+      int64_t np = 0;
+      if ((rc = grad_range(t, *grad, st.d_keys[b], st.d_vals[b], lo, cnt, factors, factor_dtype,
+                           rank, outs, st.d_res[b], t->d_partials + poff, &np, s)))
         return rc;
+      poff += np;
+    } else {
+      for (int m = 0; m < L.N; ++m) {
+        if (!outs[m]) continue;
+        if ((rc = launch_mttkrp(t, st.d_keys[b], st.d_vals[b], lo, cnt, m, factors, factor_dtype,
+                                rank, 1.0f, nullptr, outs[m], s)))
+          return rc;
+      }
     }
     HIPCHK(hipEventRecord(ev[3], s));
     HIPCHK(hipEventRecord((hipEvent_t)st.ev_free[b], s));
+  }
+  if (grad) {
+    hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(1024), 0, s, (const double*)t->d_partials,
+                       poff, grad->loss);
+    HIPCHK(hipGetLastError());
   }
   st.timed_chunks = chunks;
   t->stream_peak_bytes = fixed + 2 * (size_t)cap * per_nnz;
@@ -1535,6 +1799,61 @@ extern "C" int blco_mttkrp_stream_all(blco_tensor* t, const void* const* factors
                       (hipStream_t)stream);
 }
 
+extern "C" int blco_cp_grad(blco_tensor* t, const void* const* factors, int factor_dtype,
+                            int rank, const double* scale, double alpha, float* residual,
+                            double* loss, float* const* grads, size_t device_budget_bytes,
+                            void* stream) {
+  clear_error();
+  if (!t) return set_error(BLCO_EINVAL, "tensor is NULL");
+  if (!loss) return set_error(BLCO_EINVAL, "loss is NULL");
+  if (!grads) return set_error(BLCO_EINVAL, "grads is NULL");
+  if (!factors) return set_error(BLCO_EINVAL, "factors is NULL");
+  const int N = t->lay.N;
+  float* o[BLCO_MAX_MODES] = {};
+  for (int m = 0; m < N; ++m) {
+    o[m] = grads[m];
+    if (!o[m]) return set_error(BLCO_EINVAL, "grads[%d] is NULL", m);
+    if (!factors[m]) return set_error(BLCO_EINVAL, "factors[%d] is NULL", m);
+    int rc = check_factor_args(t, m, factors, factor_dtype, rank, o[m], true);
+    if (rc) return rc;
+  }
+  for (int m = 0; m < N; ++m)
+    for (int j = 0; j < N; ++j) {
+      if (j == m) continue;
+      const size_t na = (size_t)t->lay.dims[m] * rank, nb = (size_t)t->lay.dims[j] * rank;
+      if (o[m] < o[j] + nb && o[j] < o[m] + na)
+        return set_error(BLCO_EINVAL, "grads[%d] overlaps grads[%d]", m, j);
+    }
+  if (t->placement == BLCO_PLACE_DEVICE) {
+    if (!residual && t->nnz > 0) return set_error(BLCO_EINVAL, "residual is NULL");
+  } else if (t->placement == BLCO_PLACE_PINNED) {
+    if (residual)
+      return set_error(BLCO_EINVAL, "residual must be NULL for a tensor in pinned host memory");
+  } else {
+    return set_error(BLCO_EINVAL, "the CP gradient needs a tensor on the device or in pinned "
+                                  "host memory");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if (t->nnz == 0) {
+    for (int m = 0; m < N; ++m)
+      if ((rc = fill_zero(o[m], (int64_t)t->lay.dims[m] * rank, s))) return rc;
+    hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(1024), 0, s, (const double*)nullptr,
+                       (int64_t)0, loss);
+    HIPCHK(hipGetLastError());
+    return BLCO_OK;
+  }
+  GradArgs g;
+  g.m0 = -1;
+  for (int m = 0; m < N && g.m0 < 0; ++m)
+    if (fused_mode_ok(t, m, rank, factor_dtype)) g.m0 = m;
+  g.scale = (float)(-alpha);
+  g.scale_dev = scale;
+  g.resid = residual;
+  g.loss = loss;
+  return stream_modes(t, factors, factor_dtype, rank, o, device_budget_bytes, s, &g);
+}
+
 extern "C" int blco_sampled_loss(blco_tensor* t, const void* const* factors, int factor_dtype,
                                  int rank, float* residual, double* loss, void* stream) {
   clear_error();
@@ -1557,42 +1876,12 @@ extern "C" int blco_sampled_loss(blco_tensor* t, const void* const* factors, int
     HIPCHK(hipGetLastError());
     return BLCO_OK;
   }
-  int64_t tiles = (t->nnz + 63) / 64;
-  int64_t blocks = (tiles + kWaves - 1) / kWaves;
-  if (t->partials_cap < blocks) {
-    if (t->d_partials) {
-      HIPCHK(hipStreamSynchronize(s));
-      HIPCHK(hipFree(t->d_partials));
-      t->d_partials = nullptr;
-      t->partials_cap = 0;
-    }
-    HIPCHK(hipMalloc((void**)&t->d_partials, sizeof(double) * (size_t)blocks));
-    t->partials_cap = blocks;
-  }
-  KParams p;
-  fill_params(t, &p);
-  p.keys = t->d_keys;
-  p.vals = t->d_vals;
-  p.base = 0;
-  p.n = t->nnz;
-  for (int m = 0; m < t->lay.N; ++m) p.A[m] = factors[m];
-  p.out = residual;
-  p.partials = t->d_partials;
-  p.R = rank;
-  p.mode = -1;
-  // factors below 4 GiB are gathered with 32-bit byte offsets, larger ones
-  // with 64-bit addresses
-  const size_t fsz = factor_elem_bytes(factor_dtype);
-  p.rowbytes = (uint32_t)((size_t)rank * fsz);
-  bool big = (size_t)rank * fsz >= (1ULL << 31);
-  for (int m = 0; m < t->lay.N; ++m) {
-    const size_t bytes = (size_t)t->lay.dims[m] * rank * fsz;
-    p.abytes[m] = (uint32_t)std::min<size_t>(bytes, 0xFFFFFFFFull);
-    if (bytes > 0xFFFFFFFFull) big = true;
-  }
-  KernelFn f = select_loss(t->lay.N, rank, factor_dtype, big);
-  hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(kBlock), 0, s, p);
-  HIPCHK(hipGetLastError());
+  const int64_t blocks = loss_blocks(t->nnz);
+  int rc;
+  if ((rc = ensure_partials(t, blocks, s))) return rc;
+  if ((rc = launch_loss(t, t->d_keys, t->d_vals, 0, t->nnz, factors, factor_dtype, rank, residual,
+                        t->d_partials, s)))
+    return rc;
   hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(1024), 0, s, (const double*)t->d_partials,
                      blocks, loss);
   HIPCHK(hipGetLastError());
@@ -1610,6 +1899,19 @@ extern "C" int blco_atomic_probe(float* out, int64_t nrows, int rank, const uint
   if (blocks > 0x7FFFFFFF) return set_error(BLCO_EINVAL, "n = %lld too large", (long long)n);
   hipLaunchKernelGGL(k_atomic_probe, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                      out, nrows, rows, n, rank);
+  HIPCHK(hipGetLastError());
+  return BLCO_OK;
+}
+
+extern "C" int blco_scale(float* x, int64_t n, const double* scale, double alpha,
+                          void* stream) {
+  clear_error();
+  if (n < 0) return set_error(BLCO_EINVAL, "n = %lld < 0", (long long)n);
+  if (n == 0) return BLCO_OK;
+  if (!x) return set_error(BLCO_EINVAL, "x is NULL");
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, x, n,
+                     scale, alpha);
   HIPCHK(hipGetLastError());
   return BLCO_OK;
 }

@@ -33,7 +33,9 @@ struct StreamState {
   void* ev_free[2] = {nullptr, nullptr};
   uint64_t* d_keys[2] = {nullptr, nullptr};
   float* d_vals[2] = {nullptr, nullptr};
+  float* d_res[2] = {nullptr, nullptr};   // residual of each staged chunk (CP gradient)
   int64_t cap_nnz = 0;             // non-zeros per staging buffer
+  int64_t res_cap = 0;             // non-zeros per residual buffer
   // timing events of the last call: per chunk copy start/end (copy stream)
   // and kernel start/end (caller's stream)
   std::vector<void*> ev_t;         // 4 per chunk

@@ -23,6 +23,7 @@ struct KParams {
   int multi;                  // more than one run (else every base is 0)
   const void* A[8];           // factor matrices (A[mode] unused by MTTKRP)
   float* out;                 // MTTKRP: I_mode x R; loss: residual (nnz)
+  float* resid;               // fused residual walk: residual of each non-zero (n)
   double* partials;           // loss: one fp64 partial sum per workgroup
   int R;
   int mode;
