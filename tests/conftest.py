@@ -32,3 +32,24 @@ def fig4a():
     c = np.array([[int(r[0]) - 1, int(r[1]) - 1, int(r[2]) - 1] for r in rows], dtype=np.uint32)
     v = np.array([float(r[3]) for r in rows], dtype=np.float32)
     return [np.ascontiguousarray(c[:, m]) for m in range(3)], v, (4, 4, 4)
+
+
+# fp32 residuals in CP-gradient checks.  The library forms e_k = x_k - xhat_k in fp32 with
+# xhat_k = sum_r prod_m A^(m)[i_m^k, r]: N - 1 products per rank and a sum of R terms, in
+# whatever order its kernel uses, so |fl(xhat_k) - xhat_k| <= gamma_{N+R-1} sum_r prod_m |a|
+# (gamma_n = n u / (1 - n u), u = 2^-24, any summation order), and the difference adds
+# u |e_k|.  A gradient entry sums e_k prod_{m != n} a, so on top of the relative bound on
+# its own summation (TOL times the sum of |terms|) it may move by gamma_{N+R} W, with
+# W = MTTKRP_n(sum_r prod_m |a|; |A|): the model's magnitude, not the residual's, which a
+# near-cancelling residual in a row of few non-zeros exposes.  residual_gamma(N, R) is that
+# gamma, rounded up.
+def residual_gamma(N, R):
+    n = N + R + 1
+    u = 2.0 ** -24
+    return n * u / (1 - n * u)
+
+
+def grad_allowed(S, W, N, R, tol=1e-5):
+    """Allowed |gpu - oracle| of CP-gradient entries: tol * S (S the sum of |e-terms|) plus
+    the fp32 residual's rounding carried through the MTTKRP (W as above)."""
+    return tol * S + residual_gamma(N, R) * W

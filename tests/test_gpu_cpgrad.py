@@ -3,7 +3,8 @@
 The loss is 1/2 sum_k e_k^2 with e_k = x_k - xhat_k (Section 2.2 model) and the
 gradient with respect to A^(n) is -MTTKRP_n(E): the oracle composes its CP loss and
 its MTTKRP (oracle.cp_grad), both pinned on the CPU.  Acceptance: loss within 1e-6
-relative; each gradient entry within 1e-5 of the sum of |terms|; the residual within
+relative; each gradient entry within 1e-5 of the sum of |terms| plus the fp32
+residual's rounding through the model's magnitude (conftest.grad_allowed); the residual within
 1e-5 of |x_k| + sum_r prod_m |a| (its fp32 rounding).  Cases cover the fused walk
 (register-based modes, R <= 64), the fallback through the sampled-loss kernel (every
 mode hierarchical, or R > 64), frequent-row stashes, blocked keys, out-of-memory
@@ -21,19 +22,22 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import oracle  # noqa: E402
+from conftest import grad_allowed  # noqa: E402
 import paper_2201_12523_amd as blco  # noqa: E402
 
 DEV = torch.device("cuda:0")
 TOL = 1e-5
 
 
-def check(got, M, S, label, tol=TOL):
+def check(got, M, S, W, N, R, label):
+    """Gradient entries within grad_allowed: TOL of the sum of |terms| plus the fp32
+    residual's rounding through the model's magnitude W."""
     got = np.asarray(got, dtype=np.float64)
     zero = S == 0
     assert np.all(got[zero] == 0.0), f"{label}: non-zero where no term lands"
-    err = np.abs(got - M)[~zero] / S[~zero]
-    worst = float(err.max()) if err.size else 0.0
-    assert worst <= tol, f"{label}: max normalised error {worst:.3e}"
+    lim = grad_allowed(S, W, N, R, TOL)
+    worst = float((np.abs(got - M)[~zero] / lim[~zero]).max()) if (~zero).any() else 0.0
+    assert worst <= 1.0, f"{label}: max error / allowed {worst:.3e}"
 
 
 def make(dims, nnz, seed, hot=False):
@@ -65,8 +69,12 @@ def run(coords, vals, dims, R, rng, storage="fp32", placement="device", resoluti
     lab = f"dims={dims} R={R} {storage} {placement} {resolution}"
     assert abs(float(loss) - f) <= 1e-6 * f, (lab, float(loss), f)
     k = alpha * (1.0 if scale is None else scale)
+    Aabs = [np.abs(a).astype(np.float64) for a in Aref]
+    xabs = oracle.cp_model(coords, Aabs)
     for n in range(N):
-        check(grads[n].cpu().numpy(), k * G[n], abs(k) * S[n], f"{lab} grad mode {n}")
+        W, _ = oracle.mttkrp(coords, xabs, Aabs, n, dims=dims)
+        check(grads[n].cpu().numpy(), k * G[n], abs(k) * S[n], abs(k) * W, N, R,
+              f"{lab} grad mode {n}")
     if resid is not None:
         order = oracle.encode.encode(coords, vals, dims, key_bits=key_bits)["order"]
         xabs = oracle.cp_model([c[order] for c in coords],
@@ -125,9 +133,12 @@ def test_streamed_many_chunks(storage):
     coords, vals, rng = make(dims, nnz, 35, hot=True)
     R = 32
 
+    sf = 4 if storage == "fp32" else 2   # bytes per stored factor element
+
     def budget(t):
-        # every factor and gradient, the tables, and two buffers of ~3000 non-zeros
-        return sum(d * R * 4 * 2 for d in dims) + t.info()["device_bytes"] + 2 * 3000 * 16
+        # every factor (sf bytes per element) and fp32 gradient, the tables, and two
+        # buffers of ~3000 non-zeros (key, value, residual)
+        return sum(d * R * (sf + 4) for d in dims) + t.info()["device_bytes"] + 2 * 3000 * 16
 
     t, loss, grads = run(coords, vals, dims, R, rng, storage, placement="pinned",
                          budget=budget, hot_min_count=1)
@@ -144,8 +155,12 @@ def test_cploss_backward_scales_by_the_incoming_gradient():
     loss = blco.CPLoss.apply(t, "fp32", *P)
     (2.5 * loss).backward()
     f, e, G, S = oracle.cp_grad(coords, vals, [a.astype(np.float64) for a in A])
+    Aabs = [np.abs(a).astype(np.float64) for a in A]
+    xabs = oracle.cp_model(coords, Aabs)
     for n in range(3):
-        check(P[n].grad.cpu().numpy(), 2.5 * G[n], 2.5 * S[n], f"2.5 * loss, mode {n}")
+        W, _ = oracle.mttkrp(coords, xabs, Aabs, n, dims=dims)
+        check(P[n].grad.cpu().numpy(), 2.5 * G[n], 2.5 * S[n], 2.5 * W, 3, 8,
+              f"2.5 * loss, mode {n}")
     # no gradient wanted: the loss alone
     with torch.no_grad():
         l2 = blco.CPLoss.apply(t, "fp32", *[p.detach() for p in P])
