@@ -248,6 +248,25 @@ int blco_cp_grad(blco_tensor* t, const void* const* factors, int factor_dtype, i
                  float* const* grads, size_t device_budget_bytes, void* stream);
 
 /*
+ * blco_cp_grad without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as blco_cp_grad for a tensor with DEVICE
+ * placement (there is no budget: nothing is staged).  The loss's fp64 partial
+ * sums live in a static device array of 2^19 doubles (4 MiB, held by every GPU
+ * the library runs on until the process ends) instead of memory the tensor
+ * allocates; the call reserves ceil(nnz / 256) of them (the most either of its
+ * loss reductions writes), so a tensor of at most 2^27 non-zeros is accepted and
+ * a larger one gets EUNSUPPORTED before any device work.  The array is shared by
+ * every call on a GPU and keeps the last call's contents (nothing in it needs to
+ * start at zero): calls that overlap on one GPU, from any stream or thread, race.
+ * Errors: those of blco_cp_grad, EINVAL for a tensor not on the device,
+ * EUNSUPPORTED (workspace size), EDEVICE (workspace address lookup).
+ */
+int blco_cp_grad_noalloc(blco_tensor* t, const void* const* factors, int factor_dtype, int rank,
+                         const double* scale, double alpha, float* residual, double* loss,
+                         float* const* grads, void* stream);
+
+/*
  * x[i] *= alpha * (scale ? *scale : 1) for i < n (x device fp32, scale a device
  * double or NULL): the chain-rule factor of an autograd backward applied to
  * gradients computed ahead by blco_cp_grad.  Errors: EINVAL.

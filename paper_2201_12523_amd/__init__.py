@@ -32,7 +32,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: 
 
 EXPORTED = ["blco_build", "blco_mttkrp", "blco_mttkrp_acc", "blco_mttkrp_v", "blco_mttkrp_stream",
             "blco_mttkrp_stream_all",
-            "blco_sampled_loss", "blco_cp_grad", "blco_scale", "blco_cast_bf16", "blco_set_resolution", "blco_resolution",
+            "blco_sampled_loss", "blco_cp_grad", "blco_cp_grad_noalloc", "blco_scale", "blco_cast_bf16", "blco_set_resolution", "blco_resolution",
             "blco_gram", "blco_cp_als", "blco_build_device",
             "blco_atomic_probe", "blco_frequent_rows", "blco_info", "blco_export", "blco_free",
             "blco_last_error"]
@@ -94,6 +94,7 @@ def lib():
         L.blco_cast_bf16.argtypes = [p, p, i64, p]
         L.blco_cp_grad.argtypes = [p, p, i32, i32, p, ctypes.c_double, p, p, p, ctypes.c_size_t,
                                    p]
+        L.blco_cp_grad_noalloc.argtypes = [p, p, i32, i32, p, ctypes.c_double, p, p, p, p]
         L.blco_scale.argtypes = [p, i64, p, ctypes.c_double, p]
         L.blco_info.argtypes = [p, ctypes.POINTER(_Info)]
         L.blco_export.argtypes = [p, p, p, p, p]
@@ -406,6 +407,24 @@ def cp_grad(t, factors, grads=None, residual=None, loss=None, scale=None, alpha=
                               None if pinned else residual.data_ptr(), loss.data_ptr(), ptrs,
                               int(device_budget), _stream(stream)))
     return loss, grads, (None if pinned else residual)
+
+
+def cp_grad_noalloc(t, factors, grads, residual, loss, scale=None, alpha=1.0, stream=None):
+    """cp_grad for a device tensor through the entry point that allocates nothing on the
+    device: every output (grads, residual of t.nnz floats, a float64 loss) is the caller's."""
+    arr, dt, R, _keep = _factor_args(t, factors, None)
+    N = len(t.dims)
+    if len(grads) != N:
+        raise ValueError(f"{N} gradients expected")
+    sp = None
+    if scale is not None:
+        if scale.dtype != torch.float64 or scale.numel() != 1:
+            raise ValueError("scale must be a one-element float64 device tensor")
+        sp = scale.data_ptr()
+    ptrs = (ctypes.c_void_p * N)(*[g.data_ptr() for g in grads])
+    _check(lib().blco_cp_grad_noalloc(t.handle, arr, dt, R, sp, float(alpha), residual.data_ptr(),
+                                      loss.data_ptr(), ptrs, _stream(stream)))
+    return loss, grads, residual
 
 
 def scale_(x, scale, alpha=1.0, stream=None):

@@ -1561,6 +1561,7 @@ struct GradArgs {
   const double* scale_dev;  // optional device-side scale
   float* resid;             // DEVICE placement: the caller's residual (nnz)
   double* loss;             // device: 1/2 sum of squared residuals
+  double* partials;         // DEVICE placement: workspace of partial sums, NULL: the tensor's
 };
 
 // Residual and gradients of one range [lo, lo + n) whose keys/vals are given;
@@ -1620,12 +1621,16 @@ static int stream_modes(blco_tensor* t, const void* const* factors, int factor_d
   if (t->placement == BLCO_PLACE_DEVICE && grad) {
     for (int m = 0; m < L.N; ++m)
       if ((rc = fill_zero(outs[m], (int64_t)L.dims[m] * rank, s))) return rc;
-    if ((rc = ensure_partials(t, grad_parts(t->nnz), s))) return rc;
+    double* part = grad->partials;
+    if (!part) {
+      if ((rc = ensure_partials(t, grad_parts(t->nnz), s))) return rc;
+      part = t->d_partials;
+    }
     int64_t np = 0;
     if ((rc = grad_range(t, *grad, t->d_keys, t->d_vals, 0, t->nnz, factors, factor_dtype, rank,
-                         outs, grad->resid, t->d_partials, &np, s)))
+                         outs, grad->resid, part, &np, s)))
       return rc;
-    hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(1024), 0, s, (const double*)t->d_partials, np,
+    hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(1024), 0, s, (const double*)part, np,
                        grad->loss);
     HIPCHK(hipGetLastError());
     t->stream_peak_bytes = fixed;
@@ -1799,15 +1804,46 @@ extern "C" int blco_mttkrp_stream_all(blco_tensor* t, const void* const* factors
                       (hipStream_t)stream);
 }
 
-extern "C" int blco_cp_grad(blco_tensor* t, const void* const* factors, int factor_dtype,
-                            int rank, const double* scale, double alpha, float* residual,
-                            double* loss, float* const* grads, size_t device_budget_bytes,
-                            void* stream) {
+// ---- workspace of blco_cp_grad_noalloc: the fp64 partial sums of the loss live in
+// a static device array instead of memory the tensor allocates.  Each device holds
+// its own copy; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (the array's name is not a device address there).
+constexpr int64_t kScratchParts = 1 << 19;   // 4 MiB of fp64 partial sums per device
+static __device__ __align__(256) double scratch[kScratchParts];
+constexpr int kScratchDevs = 64;
+
+// Device address of `scratch` on the current device, looked up once per device.
+static int scratch_ptr(double** out) {
+  static std::mutex mu;
+  static double* addr[kScratchDevs] = {};
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevs)
+    return set_error(BLCO_EDEVICE, "device %d outside 0..%d", dev, kScratchDevs - 1);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_error(BLCO_EDEVICE, "no device address for the workspace on device %d", dev);
+    addr[dev] = static_cast<double*>(p);
+  }
+  *out = addr[dev];
+  return BLCO_OK;
+}
+
+// blco_cp_grad and blco_cp_grad_noalloc; with noalloc the tensor must be on the
+// device and the partial sums go to the static workspace.
+static int cp_grad_impl(blco_tensor* t, const void* const* factors, int factor_dtype, int rank,
+                        const double* scale, double alpha, float* residual, double* loss,
+                        float* const* grads, size_t device_budget_bytes, void* stream,
+                        bool noalloc) {
   clear_error();
   if (!t) return set_error(BLCO_EINVAL, "tensor is NULL");
   if (!loss) return set_error(BLCO_EINVAL, "loss is NULL");
   if (!grads) return set_error(BLCO_EINVAL, "grads is NULL");
   if (!factors) return set_error(BLCO_EINVAL, "factors is NULL");
+  if (noalloc && t->placement != BLCO_PLACE_DEVICE)
+    return set_error(BLCO_EINVAL, "the allocation-free CP gradient needs a tensor on the device");
   const int N = t->lay.N;
   float* o[BLCO_MAX_MODES] = {};
   for (int m = 0; m < N; ++m) {
@@ -1833,8 +1869,15 @@ extern "C" int blco_cp_grad(blco_tensor* t, const void* const* factors, int fact
     return set_error(BLCO_EINVAL, "the CP gradient needs a tensor on the device or in pinned "
                                   "host memory");
   }
+  if (noalloc && grad_parts(t->nnz) > kScratchParts)
+    return set_error(BLCO_EUNSUPPORTED, "%lld non-zeros need %lld partial sums; the static workspace "
+                                  "holds %lld (at most %lld non-zeros are always accepted)",
+                     (long long)t->nnz, (long long)grad_parts(t->nnz), (long long)kScratchParts,
+                     (long long)kScratchParts * kBlock);
   hipStream_t s = (hipStream_t)stream;
   int rc;
+  double* ws = nullptr;
+  if (noalloc && (rc = scratch_ptr(&ws))) return rc;
   if (t->nnz == 0) {
     for (int m = 0; m < N; ++m)
       if ((rc = fill_zero(o[m], (int64_t)t->lay.dims[m] * rank, s))) return rc;
@@ -1851,7 +1894,23 @@ extern "C" int blco_cp_grad(blco_tensor* t, const void* const* factors, int fact
   g.scale_dev = scale;
   g.resid = residual;
   g.loss = loss;
+  g.partials = ws;
   return stream_modes(t, factors, factor_dtype, rank, o, device_budget_bytes, s, &g);
+}
+
+extern "C" int blco_cp_grad(blco_tensor* t, const void* const* factors, int factor_dtype,
+                            int rank, const double* scale, double alpha, float* residual,
+                            double* loss, float* const* grads, size_t device_budget_bytes,
+                            void* stream) {
+  return cp_grad_impl(t, factors, factor_dtype, rank, scale, alpha, residual, loss, grads,
+                      device_budget_bytes, stream, false);
+}
+
+extern "C" int blco_cp_grad_noalloc(blco_tensor* t, const void* const* factors, int factor_dtype,
+                                    int rank, const double* scale, double alpha, float* residual,
+                                    double* loss, float* const* grads, void* stream) {
+  return cp_grad_impl(t, factors, factor_dtype, rank, scale, alpha, residual, loss, grads, 0,
+                      stream, true);
 }
 
 extern "C" int blco_sampled_loss(blco_tensor* t, const void* const* factors, int factor_dtype,
