@@ -204,10 +204,13 @@ def counter_row_ops(counters, kernel):
             "requests": k["TCC_EA0_ATOMIC_sum"]}
 
 
+SUMMARY_KERNELS = ("k_mttkrp", "k_atomic_probe", "k_loss_tile")
+
+
 def summarize_counters(out, title, *csvs, copy_bytes=0, probe_row_ops=0, commands=()):
-    """Mean per dispatch of every counter of every kernel in rocprofv3 --pmc CSVs, written
-    as `kernel | counter | dispatches | mean`.  The largest device copy is recorded as
-    `calibration_copy` (its size is copy_bytes)."""
+    """Mean per dispatch of every counter of the MTTKRP, loss and atomic-probe kernels in
+    rocprofv3 --pmc CSVs, written as `kernel | counter | dispatches | mean`.  The largest
+    device copy is recorded as `calibration_copy` (its size is copy_bytes)."""
     import csv
 
     vals = {}
@@ -217,6 +220,8 @@ def summarize_counters(out, title, *csvs, copy_bytes=0, probe_row_ops=0, command
             name, c, v = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
             if "copyBuffer" in name:
                 copies.setdefault(c, []).append(v)
+                continue
+            if not any(k in name for k in SUMMARY_KERNELS):
                 continue
             vals.setdefault((name, c), []).append(v)
     lines = [f"# {title}", "# rocprofv3 counters, mean per dispatch. Commands, one pass each:"]
@@ -255,7 +260,8 @@ def win_kernel_name(R, N, ft="float", big=False, stash=True):
     (stash: the mode's frequent rows are held in LDS)."""
     lpn, rpl = (16, 1) if R <= 16 else (16, 2) if R <= 32 else (16, 4) if R <= 64 else (64, 2)
     b = lambda v: "true" if v else "false"
-    return f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {b(big)}, {b(stash)}>"
+    # the last template argument selects the fused CP-gradient walk, never the plain MTTKRP
+    return f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {b(big)}, {b(stash)}, false>"
 
 
 def short_kernel_name(R, N, ft="float", big=False):
@@ -726,6 +732,49 @@ def resolution_sweep(args, torch, blco, synth):
             "cus": torch.cuda.get_device_properties(0).multi_processor_count, "rows": rows}
 
 
+def leg_build(args, torch, blco, synth, w):
+    """BLCO construction alone (Section 4): the host builder once, and the GPU builder
+    (blco_build_device) from device-resident coordinates and values, `steps` times after
+    `warmup` builds, with its per-stage stream times (linearize, sort, re-encode, runs of
+    block keys, frequent rows)."""
+    dev = torch.device("cuda:0")
+    coords, vals = synth.workload_tensor(w, nnz=args.nnz, log=log)
+    nnz = len(vals)
+    t0 = time.time()
+    Th = blco.build(coords, vals, w.dims, placement="host")
+    host_s = time.time() - t0
+    inf = Th.info()
+    Th.free()
+    log(f"{w.name}: host builder {host_s:.3f}s")
+    dc = [torch.from_numpy(c.view(np.int32)).to(dev) for c in coords]
+    dv = torch.from_numpy(vals).to(dev)
+    torch.cuda.synchronize()
+    totals, stages = [], []
+    for i in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        Tg = blco.build_device(dc, dv, w.dims)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        st = Tg.info()["build_stage_ms"]
+        Tg.free()
+        if i >= args.warmup:
+            totals.append(dt * 1e3)
+            stages.append(st)
+            log(f"{w.name}: GPU build {dt * 1e3:.2f} ms, stages {st}")
+    med = {k: float(np.median([x[k] for x in stages])) for k in stages[0]}
+    ms = float(np.median(totals))
+    res = base_result(args, w, nnz, nnz / (ms * 1e-3) / 1e9, ms)
+    res["metric"] = "BLCO construction (GPU builder) non-zeros per second"
+    res["unit"] = "Gnnz/s"
+    res["config"].update({"key_bits": inf["total_bits"], "blocks": inf["nblocks"],
+                          "runs": inf["nruns"]})
+    res["build_gpu_ms"] = totals
+    res["build_stage_ms_median"] = med
+    res["build_host_s"] = host_s
+    return res
+
+
 def secondary_summary(r):
     keep = ("metric", "value", "unit", "ms_per_step", "steps", "warmup", "config", "roofline",
             "per_config", "errors", "per_mode", "one_pass", "per_mode_passes_ms_per_step",
@@ -788,6 +837,8 @@ def main():
     ap.add_argument("--cpu-sample-all-nnz", type=int, default=16_000_000,
                     help="non-zeros of the all-core oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--build-only", action="store_true",
+                    help="time BLCO construction of --workload (host and GPU builders) only")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle row checks")
     ap.add_argument("--oom-start-limit-s", type=float, default=300.0,
                     help="default run: skip the 1.5B-non-zero leg when it would start later")
@@ -824,7 +875,9 @@ def main():
         return
     W = synth.WORKLOADS
     check, cpu = not args.no_check, not args.no_cpu_baseline
-    if args.workload is None:
+    if args.build_only:
+        res = leg_build(args, torch, blco, synth, W[args.workload or "zipf3"])
+    elif args.workload is None:
         res = suite(args, torch, blco, synth)
     elif args.workload == "oom3":
         res = leg_oom(args, torch, blco, synth, W["oom3"], check=check, cpu=cpu)

@@ -98,6 +98,9 @@ typedef struct {
   double stream_kernel_ms;   /* last streaming call: MTTKRP kernel time, summed over chunks */
   double stream_total_ms;    /* last streaming call: first copy start to last kernel end */
   int hot_rows[BLCO_MAX_MODES]; /* frequent rows recorded per mode (see blco_build) */
+  double build_stage_ms[5];  /* blco_build_device: stream time of its stages (linearize,
+                                sort, re-encode, runs of block keys, frequent rows), host
+                                work in between included; 0 for blco_build */
 } blco_info_t;
 
 /*

@@ -69,7 +69,8 @@ class _Info(ctypes.Structure):
                 ("stream_peak_bytes", ctypes.c_size_t), ("stream_chunks", ctypes.c_int64),
                 ("stream_chunk_nnz", ctypes.c_int64), ("stream_copy_ms", ctypes.c_double),
                 ("stream_kernel_ms", ctypes.c_double), ("stream_total_ms", ctypes.c_double),
-                ("hot_rows", ctypes.c_int * MAX_MODES)]
+                ("hot_rows", ctypes.c_int * MAX_MODES),
+                ("build_stage_ms", ctypes.c_double * 5)]
 
 
 def library_path() -> str:
@@ -154,7 +155,9 @@ class BLCOTensor:
                     stream_peak_bytes=inf.stream_peak_bytes, stream_chunks=inf.stream_chunks,
                     stream_chunk_nnz=inf.stream_chunk_nnz, stream_copy_ms=inf.stream_copy_ms,
                     stream_kernel_ms=inf.stream_kernel_ms, stream_total_ms=inf.stream_total_ms,
-                    hot_rows=list(inf.hot_rows[:N]))
+                    hot_rows=list(inf.hot_rows[:N]),
+                    build_stage_ms=dict(zip(("linearize", "sort", "encode", "runs",
+                                             "frequent_rows"), list(inf.build_stage_ms))))
 
     @property
     def nnz(self) -> int:

@@ -2,7 +2,8 @@
 
 Host builder (``csrc/blco_host.cpp``) with g++; device runtime and MTTKRP
 kernels (``csrc/blco_device.hip``), the CP-ALS driver (``csrc/blco_cpals.hip``) and
-the GPU builder (``csrc/blco_build_gpu.hip``) with hipcc; linked with hipcc.  Run as
+the GPU builder (``csrc/blco_build_gpu.hip``) and its sort and compaction
+(``csrc/blco_sort.hip``) with hipcc; linked with hipcc.  Run as
 ``python -m paper_2201_12523_amd.buildlib``.
 """
 from __future__ import annotations
@@ -39,8 +40,9 @@ def build(verbose: bool = True) -> str:
     dev_o = os.path.join(BUILD_DIR, "blco_device.o")
     als_o = os.path.join(BUILD_DIR, "blco_cpals.o")
     gb_o = os.path.join(BUILD_DIR, "blco_build_gpu.o")
+    sort_o = os.path.join(BUILD_DIR, "blco_sort.o")
     t = time.time()
-    # the three objects compile in parallel
+    # the objects compile in parallel
     procs = [subprocess.Popen(["g++", "-std=c++17", "-O3", "-fPIC", "-Wall", "-c",
                                os.path.join(CSRC, "blco_host.cpp"), "-o", host_o]),
              subprocess.Popen([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "blco_device.hip"),
@@ -48,13 +50,15 @@ def build(verbose: bool = True) -> str:
              subprocess.Popen([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "blco_cpals.hip"),
                                "-o", als_o]),
              subprocess.Popen([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "blco_build_gpu.hip"),
-                               "-o", gb_o])]
+                               "-o", gb_o]),
+             subprocess.Popen([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "blco_sort.hip"),
+                               "-o", sort_o])]
     codes = [p.wait() for p in procs]
     if any(codes):
         raise subprocess.CalledProcessError(max(codes, key=abs), "compile")
     t1 = t2 = time.time() - t
     tmp = OUT + ".tmp"
-    t3 = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, dev_o, als_o, gb_o,
+    t3 = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", host_o, dev_o, als_o, gb_o, sort_o,
                "-o", tmp, "-lpthread"])
     os.replace(tmp, OUT)
     if verbose:

@@ -5,20 +5,21 @@
 //   1. ALTO linearization of every coordinate (Section 4.1): bit j of mode n
 //      goes to position pos[n][j] of a 64- or 128-bit index (per-byte deposit
 //      tables); out-of-range coordinates are flagged;
-//   2. a stable radix sort of (index, non-zero number) pairs: one pass over the
-//      low 64 bits, then, for indices over 64 bits, one over the high bits of
-//      the indices gathered in that order (least significant digits first);
+//   2. a stable radix sort of (index, non-zero number) pairs (blco_sort.hip):
+//      one sort over the low 64 bits, then, for indices over 64 bits, one over
+//      the high bits of the indices gathered in that order (least significant
+//      digits first);
 //   3. re-encoding in sorted order (Figure 6b) from the sorted index: every
 //      index bit below K moves to its mode's field (a byte table), the block
-//      key is the index above bit K, and the values follow the permutation;
-//   4. runs of equal block key (flags and a select), copied to the host, where
+//      key is the index above bit K; the values rode along in the sort (index
+//      of at most 64 bits) or follow the permutation (wider index);
+//   4. runs of equal block key (flags and a stream compaction), copied to the host, where
 //      the block list, per-run high bits and tile table are finished by the
 //      same code as the host builder;
 //   5. the frequent rows of each mode (sampled rows sorted and run-length
-//      counted, then a descending radix sort of the counts).
+//      counted, then a stable descending radix sort of the counts).
 // The result equals blco_build's bit for bit.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstdint>
@@ -50,18 +51,25 @@ struct LinParams {
   int T;
 };
 
-// ALTO index of every non-zero (lo: bits 0..63, hi: bits 64..127) and its
-// number; *bad = smallest non-zero number with a coordinate out of range.
-// dep[((m * 4 + k) * 256 + v) * 2 + {0, 1}]: the (lo, hi) index bits of byte k
-// of a mode-m coordinate holding v.
+// ALTO index of every non-zero (lo: bits 0..63, hi: bits 64..127 or NULL) and,
+// when idx is given, its number; *bad = smallest non-zero number with a
+// coordinate out of range.  dep[((m * 4 + k) * 256 + v) * 2 + {0, 1}]: the
+// (lo, hi) index bits of byte k of a mode-m coordinate holding v.  With hi ==
+// NULL the lo halves of the table are staged in LDS (N * 8 KiB of dynamic LDS),
+// once per workgroup of a grid that strides over the non-zeros.
 __global__ __launch_bounds__(256) void k_linearize(LinParams p, int64_t n,
                                                    const uint64_t* __restrict__ dep,
                                                    uint64_t* __restrict__ lo,
                                                    uint64_t* __restrict__ hi,
                                                    uint32_t* __restrict__ idx,
                                                    unsigned long long* __restrict__ bad) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
+  extern __shared__ uint64_t s_dep[];   // [(m * 4 + k) * 256 + v], lo halves (hi == NULL)
+  if (!hi) {
+    for (int j = threadIdx.x; j < p.N * 4 * 256; j += 256) s_dep[j] = dep[2 * j];
+    __syncthreads();
+  }
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
   uint64_t l = 0, h = 0;
   for (int m = 0; m < p.N; ++m) {
     uint32_t c = p.coords[m][i];
@@ -69,17 +77,24 @@ __global__ __launch_bounds__(256) void k_linearize(LinParams p, int64_t n,
       atomicMin(bad, (unsigned long long)i);
       c = 0;
     }
-    const uint64_t* d = dep + (size_t)m * 4 * 256 * 2;
+    if (!hi) {
+      const uint64_t* d = s_dep + (size_t)m * 4 * 256;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t v = (c >> (8 * k)) & 255u;
-      l |= d[(k * 256 + v) * 2];
-      h |= d[(k * 256 + v) * 2 + 1];
+      for (int k = 0; k < 4; ++k) l |= d[k * 256 + ((c >> (8 * k)) & 255u)];
+    } else {
+      const uint64_t* d = dep + (size_t)m * 4 * 256 * 2;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t v = (c >> (8 * k)) & 255u;
+        l |= d[(k * 256 + v) * 2];
+        h |= d[(k * 256 + v) * 2 + 1];
+      }
     }
   }
   lo[i] = l;
   if (hi) hi[i] = h;
-  idx[i] = (uint32_t)i;
+  if (idx) idx[i] = (uint32_t)i;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_gather_u64(const uint64_t* __restrict__ src,
@@ -113,7 +128,8 @@ __global__ __launch_bounds__(256) void k_encode(int64_t n, int K, const uint64_t
 #pragma unroll
   for (int k = 0; k < kEncBytes; ++k) key |= s_enc[k * 256 + ((low >> (8 * k)) & 255)];
   keys[i] = key;
-  vout[i] = vals[perm[i]];
+  if (perm) vout[i] = vals[perm[i]];   // else the sort already moved the values
+  if (!bkey) return;
   uint64_t B;
   if (K >= 64)
     B = h >> (K - 64);
@@ -143,9 +159,56 @@ __global__ __launch_bounds__(256) void k_sample(const uint32_t* __restrict__ c, 
   if (s < samples) out[s] = c[s * step];
 }
 
+__global__ __launch_bounds__(256) void k_row_flags(const uint32_t* __restrict__ sorted, int64_t n,
+                                                   uint8_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) flag[i] = (i == 0 || sorted[i] != sorted[i - 1]) ? 1 : 0;
+}
+
+// Run-length encoding from the run starts of a sorted array: the value and the
+// length of every run.
+__global__ __launch_bounds__(256) void k_runs(const uint32_t* __restrict__ sorted,
+                                              const int64_t* __restrict__ starts, int64_t nruns,
+                                              int64_t n, uint32_t* __restrict__ uniq,
+                                              uint32_t* __restrict__ cnt) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= nruns) return;
+  const int64_t a = starts[r], e = r + 1 < nruns ? starts[r + 1] : n;
+  uniq[r] = sorted[a];
+  cnt[r] = (uint32_t)(e - a);
+}
+
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v) { *p = v; }
 
 unsigned grid_of(int64_t n) { return (unsigned)std::max<int64_t>((n + 255) / 256, 1); }
+
+constexpr unsigned kStrideGrid = 2048;   // workgroups of grid-stride kernels (8 per CU)
+
+// Events at the stage boundaries of one build on its stream (released on return).
+struct StageEvents {
+  static constexpr int kN = 6;
+  hipEvent_t ev[kN] = {};
+  bool ok = true;
+  StageEvents() {
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) ok = false;
+  }
+  ~StageEvents() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void mark(int k, hipStream_t s) {
+    if (ok) (void)hipEventRecord(ev[k], s);
+  }
+  // elapsed ms between consecutive marks, once the last has completed
+  void read(double* ms) {
+    if (!ok || hipEventSynchronize(ev[kN - 1]) != hipSuccess) return;
+    for (int k = 0; k + 1 < kN; ++k) {
+      float x = 0.f;
+      if (hipEventElapsedTime(&x, ev[k], ev[k + 1]) == hipSuccess) ms[k] = x;
+    }
+  }
+};
 
 // device allocations released on every return path
 struct Pool {
@@ -204,20 +267,17 @@ int gpu_hot_rows(const LinParams& lp, int64_t nnz, int64_t min_count, Pool& pool
   const int64_t samples = (nnz + step - 1) / step;
   const uint64_t need = (uint64_t)std::max<int64_t>(1, (min_count + step - 1) / step);
   int rc;
-  uint32_t *smp, *sorted, *uniq, *cnt, *cnt2, *row2;
-  int64_t* nuniq;
+  uint32_t *smp, *sorted, *uniq, *cnt, *cnt2, *row2, *tk, *tv;
+  uint8_t* flag;
+  int64_t* starts;
+  unsigned int* ws;
   if ((rc = pool.get(&smp, samples)) || (rc = pool.get(&sorted, samples)) ||
       (rc = pool.get(&uniq, samples)) || (rc = pool.get(&cnt, samples)) ||
-      (rc = pool.get(&cnt2, samples)) || (rc = pool.get(&row2, samples)) || (rc = pool.get(&nuniq, 1)))
+      (rc = pool.get(&cnt2, samples)) || (rc = pool.get(&row2, samples)) ||
+      (rc = pool.get(&tk, samples)) || (rc = pool.get(&tv, samples)) ||
+      (rc = pool.get(&flag, samples)) || (rc = pool.get(&starts, samples)) ||
+      (rc = pool.get(&ws, std::max(sort_workspace_words(samples), select_workspace_words(samples)))))
     return rc;
-  void* tmp = nullptr;
-  size_t tmp_cap = 0;
-  auto need_tmp = [&](size_t bytes) -> int {
-    if (bytes <= tmp_cap) return BLCO_OK;
-    int r = pool.get((char**)&tmp, bytes);
-    if (r == BLCO_OK) tmp_cap = bytes;
-    return r;
-  };
   for (int n = 0; n < N; ++n) {
     const uint64_t I = lp.dims[n];
     if (I > ((uint64_t)1 << 26)) continue;
@@ -225,21 +285,20 @@ int gpu_hot_rows(const LinParams& lp, int64_t nnz, int64_t min_count, Pool& pool
     hipLaunchKernelGGL(k_sample, dim3(grid_of(samples)), dim3(256), 0, s, lp.coords[n], samples,
                        step, smp);
     HIPCHK(hipGetLastError());
-    size_t b1 = 0, b2 = 0, b3 = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, b1, smp, sorted, (int)samples, 0, bits, s));
-    HIPCHK(hipcub::DeviceRunLengthEncode::Encode(nullptr, b2, sorted, uniq, cnt, nuniq,
-                                                 (int)samples, s));
-    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, b3, cnt, cnt2, uniq, row2,
-                                                        (int)samples, 0, 32, s));
-    if ((rc = need_tmp(std::max(b1, std::max(b2, b3))))) return rc;
-    HIPCHK(hipcub::DeviceRadixSort::SortKeys(tmp, b1, smp, sorted, (int)samples, 0, bits, s));
-    HIPCHK(hipcub::DeviceRunLengthEncode::Encode(tmp, b2, sorted, uniq, cnt, nuniq, (int)samples,
-                                                 s));
+    // the sampled rows in order, their runs (row, count), the runs by count,
+    // most frequent first (equal counts keep ascending rows: the sort is stable)
+    if ((rc = radix_sort_u32(smp, nullptr, sorted, nullptr, tk, nullptr, samples, bits, false, ws,
+                             s)))
+      return rc;
+    hipLaunchKernelGGL(k_row_flags, dim3(grid_of(samples)), dim3(256), 0, s, sorted, samples,
+                       flag);
+    HIPCHK(hipGetLastError());
     int64_t nu = 0;
-    HIPCHK(hipMemcpyAsync(&nu, nuniq, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipcub::DeviceRadixSort::SortPairsDescending(tmp, b3, cnt, cnt2, uniq, row2, (int)nu, 0,
-                                                        32, s));
+    if ((rc = select_flagged(flag, samples, starts, &nu, ws, s))) return rc;
+    hipLaunchKernelGGL(k_runs, dim3(grid_of(nu)), dim3(256), 0, s, sorted, starts, nu, samples,
+                       uniq, cnt);
+    HIPCHK(hipGetLastError());
+    if ((rc = radix_sort_u32(cnt, uniq, cnt2, row2, tk, tv, nu, 32, true, ws, s))) return rc;
     const size_t k = std::min<size_t>((size_t)nu, kHotMax + 1);
     std::vector<uint32_t> hc(k), hr(k);
     if (k) {
@@ -279,14 +338,20 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
     for (int j = 0; j < L.b[m]; ++j) lp.pos[m][j] = (uint8_t)L.pos[m][j];
   }
   Pool pool;
+  StageEvents stage;
+  stage.mark(0, s);
   const bool wide = L.T > 64;
   uint64_t *lo, *lo2, *hi = nullptr, *hi2 = nullptr, *bkey;
-  uint32_t *idx, *perm, *perm2;
+  uint32_t *idx = nullptr, *perm = nullptr, *perm2 = nullptr;
   unsigned long long* bad;
-  if ((rc = pool.get(&lo, nnz)) || (rc = pool.get(&lo2, nnz)) || (rc = pool.get(&idx, nnz)) ||
-      (rc = pool.get(&perm, nnz)) || (rc = pool.get(&bkey, nnz)) || (rc = pool.get(&bad, 1)))
+  if ((rc = pool.get(&lo, nnz)) || (rc = pool.get(&lo2, nnz)) || (rc = pool.get(&bkey, nnz)) ||
+      (rc = pool.get(&bad, 1)))
     return rc;
-  if (wide && ((rc = pool.get(&hi, nnz)) || (rc = pool.get(&hi2, nnz)) || (rc = pool.get(&perm2, nnz))))
+  // an index over 64 bits is sorted in two parts and needs the permutation; one of
+  // at most 64 bits carries the values through its sort instead
+  if (wide && ((rc = pool.get(&hi, nnz)) || (rc = pool.get(&hi2, nnz)) ||
+               (rc = pool.get(&idx, nnz)) || (rc = pool.get(&perm, nnz)) ||
+               (rc = pool.get(&perm2, nnz))))
     return rc;
   // 1. linearize, through per-byte deposit tables
   std::vector<uint64_t> dep((size_t)L.N * 4 * 256 * 2, 0);
@@ -311,8 +376,9 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
   HIPCHK(hipMemcpyAsync(d_dep, dep.data(), dep.size() * 8, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s, bad, ~0ULL);
   if (nnz > 0)
-    hipLaunchKernelGGL(k_linearize, dim3(grid_of(nnz)), dim3(256), 0, s, lp, nnz, d_dep, lo, hi,
-                       idx, bad);
+    hipLaunchKernelGGL(k_linearize, dim3(std::min<unsigned>(grid_of(nnz), kStrideGrid)), dim3(256),
+                       wide ? 0 : (size_t)L.N * 4 * 256 * sizeof(uint64_t), s, lp, nnz, d_dep, lo,
+                       hi, idx, bad);
   HIPCHK(hipGetLastError());
   unsigned long long first_bad = ~0ULL;
   HIPCHK(hipMemcpyAsync(&first_bad, bad, 8, hipMemcpyDeviceToHost, s));
@@ -329,34 +395,39 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
     return set_error(BLCO_ERANGE, "coordinate out of range at non-zero %lld", (long long)i);
   }
   // 2. stable sort along the encoding line
+  stage.mark(1, s);
+  size_t acc = 0;
+  HIPCHK(hipMalloc((void**)&t->d_keys, sizeof(uint64_t) * std::max<int64_t>(nnz, 1)));
+  HIPCHK(hipMalloc((void**)&t->d_vals, sizeof(float) * std::max<int64_t>(nnz, 1)));
+  acc += (sizeof(uint64_t) + sizeof(float)) * (size_t)std::max<int64_t>(nnz, 1);
   uint64_t* hi_sorted = nullptr;
   if (nnz > 0) {
     const int nb0 = std::max(1, std::min(L.T, 64));
-    size_t tmp_bytes = 0, t2 = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, lo, lo2, idx, perm, (int)nnz, 0,
-                                              nb0, s));
+    uint64_t* tk;
+    uint32_t* tv;
+    unsigned int* ws;
+    if ((rc = pool.get(&tk, nnz)) || (rc = pool.get(&tv, nnz)) ||
+        (rc = pool.get(&ws, sort_workspace_words(nnz))))
+      return rc;
+    // at most 64 index bits: the values travel with the keys into the tensor
+    const uint32_t* payload = wide ? idx : reinterpret_cast<const uint32_t*>(values);
+    uint32_t* moved = wide ? perm : reinterpret_cast<uint32_t*>(t->d_vals);
+    if ((rc = radix_sort_u64(lo, payload, lo2, moved, tk, tv, nnz, nb0, ws, s))) return rc;
     if (wide) {
-      if ((rc = pool.get(&hi_sorted, nnz))) return rc;
-      HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, t2, hi2, hi_sorted, perm, perm2, (int)nnz,
-                                                0, L.T - 64, s));
-    }
-    void* tmp;
-    if ((rc = pool.get((char**)&tmp, std::max(tmp_bytes, t2)))) return rc;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, lo, lo2, idx, perm, (int)nnz, 0, nb0,
-                                              s));
-    if (wide) {
-      // the high bits in that order, a stable pass over them, then the low
+      // the high bits in that order, a stable sort over them, then the low
       // bits in the final order
+      if ((rc = pool.get(&hi_sorted, nnz))) return rc;
       hipLaunchKernelGGL(k_gather_u64, dim3(grid_of(nnz)), dim3(256), 0, s, hi, perm, nnz, hi2);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp, t2, hi2, hi_sorted, perm, perm2, (int)nnz, 0,
-                                                L.T - 64, s));
+      if ((rc = radix_sort_u64(hi2, perm, hi_sorted, perm2, tk, tv, nnz, L.T - 64, ws, s)))
+        return rc;
       std::swap(perm, perm2);
       hipLaunchKernelGGL(k_gather_u64, dim3(grid_of(nnz)), dim3(256), 0, s, lo, perm, nnz, lo2);
       HIPCHK(hipGetLastError());
     }
   }
   // 3. re-encode in sorted order; keys and values go straight into the tensor
+  stage.mark(2, s);
   std::vector<uint64_t> enc((size_t)kEncBytes * 256, 0);
   {
     int owner_mode[128], owner_bit[128];
@@ -379,36 +450,31 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
   uint64_t* d_enc;
   if ((rc = pool.get(&d_enc, enc.size()))) return rc;
   HIPCHK(hipMemcpyAsync(d_enc, enc.data(), enc.size() * 8, hipMemcpyHostToDevice, s));
-  size_t acc = 0;
-  HIPCHK(hipMalloc((void**)&t->d_keys, sizeof(uint64_t) * std::max<int64_t>(nnz, 1)));
-  HIPCHK(hipMalloc((void**)&t->d_vals, sizeof(float) * std::max<int64_t>(nnz, 1)));
-  acc += (sizeof(uint64_t) + sizeof(float)) * (size_t)std::max<int64_t>(nnz, 1);
+  // without block bits every block key is 0: no block keys to write or scan
+  const bool blocked = L.S > 0;
   if (nnz > 0) {
     hipLaunchKernelGGL(k_encode, dim3(grid_of(nnz)), dim3(256), 0, s, nnz, L.K, d_enc, lo2,
-                       hi_sorted, perm, values, t->d_keys, t->d_vals, bkey);
+                       hi_sorted, perm, values, t->d_keys, t->d_vals, blocked ? bkey : nullptr);
     HIPCHK(hipGetLastError());
   }
   // 4. runs of equal block key
+  stage.mark(3, s);
   std::vector<int64_t> run_start;
   std::vector<uint64_t> run_key;
-  if (nnz > 0) {
+  if (nnz > 0 && !blocked) {
+    run_start.assign(1, 0);
+    run_key.assign(1, 0);
+  } else if (nnz > 0) {
     uint8_t* flag;
     int64_t* starts;
-    int64_t* nsel;
     uint64_t* keys_at;
-    if ((rc = pool.get(&flag, nnz)) || (rc = pool.get(&starts, nnz)) || (rc = pool.get(&nsel, 1)))
-      return rc;
+    if ((rc = pool.get(&flag, nnz)) || (rc = pool.get(&starts, nnz))) return rc;
     hipLaunchKernelGGL(k_run_flags, dim3(grid_of(nnz)), dim3(256), 0, s, bkey, nnz, flag);
     HIPCHK(hipGetLastError());
-    hipcub::CountingInputIterator<int64_t> it(0);
-    size_t tmp_bytes = 0;
-    HIPCHK(hipcub::DeviceSelect::Flagged(nullptr, tmp_bytes, it, flag, starts, nsel, (int)nnz, s));
-    void* tmp;
-    if ((rc = pool.get((char**)&tmp, tmp_bytes))) return rc;
-    HIPCHK(hipcub::DeviceSelect::Flagged(tmp, tmp_bytes, it, flag, starts, nsel, (int)nnz, s));
+    unsigned int* ws;
+    if ((rc = pool.get(&ws, select_workspace_words(nnz)))) return rc;
     int64_t nruns = 0;
-    HIPCHK(hipMemcpyAsync(&nruns, nsel, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    if ((rc = select_flagged(flag, nnz, starts, &nruns, ws, s))) return rc;
     if ((rc = pool.get(&keys_at, nruns))) return rc;
     hipLaunchKernelGGL(k_gather_keys, dim3(grid_of(nruns)), dim3(256), 0, s, bkey, starts, nruns,
                        keys_at);
@@ -421,13 +487,16 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
   }
   finish_runs(L, nnz, run_start, run_key, cap, t);
   // 5. frequent rows
+  stage.mark(4, s);
   if ((rc = gpu_hot_rows(lp, nnz, hot_min, pool, s, t))) return rc;
+  stage.mark(5, s);
   if ((rc = upload_to(&t->d_run_start, t->run_start.data(), t->run_start.size(), s, &acc)) ||
       (rc = upload_to(&t->d_run_base, t->run_base.data(), t->run_base.size(), s, &acc)) ||
       (rc = upload_to(&t->d_tile_run, t->tile_run.data(), t->tile_run.size(), s, &acc)) ||
       (rc = upload_to(&t->d_hot, t->hot.data(), t->hot.size(), s, &acc)))
     return rc;
   HIPCHK(hipStreamSynchronize(s));
+  stage.read(t->build_stage_ms);
   t->device_bytes = acc;
   return BLCO_OK;
 }

@@ -2039,6 +2039,7 @@ extern "C" int blco_info(const blco_tensor* t, blco_info_t* info) {
     info->dims[m] = L.dims[m];
     info->hot_rows[m] = t->nhot[m];
   }
+  for (int k = 0; k < 5; ++k) info->build_stage_ms[k] = t->build_stage_ms[k];
   info->nblocks = (int64_t)t->block_id.size();
   info->nruns = (int64_t)t->run_start.size() - 1;
   info->placement = t->placement;

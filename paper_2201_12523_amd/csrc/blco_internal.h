@@ -79,6 +79,7 @@ struct blco_tensor {
   std::vector<uint64_t> hot_cnt;     // N * (kHotMax + 1): estimated counts of the most frequent rows
   int nhot[BLCO_MAX_MODES] = {};
   bool hot_forced = false;           // an explicit threshold: stash whatever fits
+  double build_stage_ms[5] = {};     // blco_build_device stage times (blco_info_t)
   uint32_t* d_hot = nullptr;
 };
 
@@ -112,5 +113,29 @@ int make_layout(int N, const uint64_t* dims, int key_bits, Layout* L);
 // block key (run_start without the final nnz; run_key their block keys).
 void finish_runs(const Layout& L, int64_t nnz, const std::vector<int64_t>& run_start,
                  const std::vector<uint64_t>& run_key, int64_t max_block_nnz, blco_tensor* t);
+
+// Device sorting and compaction of the GPU builder (blco_sort.hip), ordered on
+// stream s (a hipStream_t, void* here so the host builder needs no HIP header).
+// The sort waits for s once (to read its digit counts) and returns with its
+// passes queued; the selection waits for s to return the count.
+//
+// Stable ascending radix sort of n < 2^31 keys over bits [0, bits) (bits beyond
+// them must be zero), with u32 values when vin != NULL: (kin, vin) -> (kout, vout),
+// the input is only read, (ktmp, vtmp) are spares of n entries, ws holds
+// sort_workspace_words(n) words.  The u32 form can sort descending (on the
+// complemented key, still stable).
+size_t sort_workspace_words(int64_t n);
+int radix_sort_u64(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
+                   uint64_t* ktmp, uint32_t* vtmp, int64_t n, int bits, unsigned int* ws,
+                   void* s);
+int radix_sort_u32(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                   uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits, bool descending,
+                   unsigned int* ws, void* s);
+
+// The indices i < n with flag[i] != 0, ascending, into out; their number into
+// *count (host).  ws holds select_workspace_words(n) words.
+size_t select_workspace_words(int64_t n);
+int select_flagged(const uint8_t* flag, int64_t n, int64_t* out, int64_t* count,
+                   unsigned int* ws, void* s);
 
 }  // namespace blco

@@ -38,11 +38,29 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_kernel_names(bench):
-    assert bench.win_kernel_name(32, 3) == "k_mttkrp_win<16, 2, float, 3, false, true>"
+    assert bench.win_kernel_name(32, 3) == "k_mttkrp_win<16, 2, float, 3, false, true, false>"
     assert bench.win_kernel_name(16, 4, "uint16_t", False, False) == \
-        "k_mttkrp_win<16, 1, uint16_t, 4, false, false>"
-    assert bench.win_kernel_name(64, 3, big=True) == "k_mttkrp_win<16, 4, float, 3, true, true>"
+        "k_mttkrp_win<16, 1, uint16_t, 4, false, false, false>"
+    assert bench.win_kernel_name(64, 3, big=True) == "k_mttkrp_win<16, 4, float, 3, true, true, false>"
     assert bench.short_kernel_name(32, 4) == "k_mttkrp_short<2, float, 4, false>"
+
+
+def test_kernel_names_exist_in_the_library(bench):
+    """The names the bench reads counters and statistics by are the library's kernels."""
+    so = os.path.join(ROOT, "paper_2201_12523_amd", "libblco.so")
+    if not os.path.exists(so):
+        pytest.skip("library not built")
+    syms = subprocess.run(["nm", "-C", so], capture_output=True, text=True, check=True).stdout
+    names = set()
+    for line in syms.splitlines():
+        if line.endswith("(blco::KParams)") or line.endswith("(blco::KParams, long)"):
+            names.add(line.split(" ", 2)[2].removeprefix("void ").split("(")[0])
+    for R in (16, 32, 64):
+        for N in (3, 4):
+            for ft in ("float", "unsigned short"):
+                for stash in (True, False):
+                    assert bench.win_kernel_name(R, N, ft, False, stash) in names
+                assert bench.short_kernel_name(R, N, ft) in names
 
 
 def test_counters_traffic_and_atomics(bench, tmp_path):
