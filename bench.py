@@ -253,6 +253,43 @@ def summarize_stats(out, title, stats_csv, command):
     print("\n".join(lines[:20]))
 
 
+def summarize_overlap(out, title, copy_csv, kernel_csv, per_call_copies, command):
+    """Copy/compute overlap of streamed MTTKRP calls from a rocprofv3 --kernel-trace
+    --memory-copy-trace run: the host-to-device copies of the library's copy stream (the
+    stream with the most copy time) taken in groups of per_call_copies (2 per chunk: keys
+    and values), the MTTKRP kernels between one group's first copy and the next group's;
+    per call t_copy = sum of its copy times, t_comp = sum of its kernel times, t_total =
+    last end - first copy start, overlap = (t_copy + t_comp - t_total) / min(t_copy, t_comp)."""
+    import csv
+
+    cps = [r for r in csv.DictReader(open(copy_csv)) if "HOST_TO_DEVICE" in r["Direction"]]
+    by_stream = {}
+    for r in cps:
+        by_stream.setdefault(r["Stream_Id"], []).append((int(r["Start_Timestamp"]),
+                                                         int(r["End_Timestamp"])))
+    copies = sorted(max(by_stream.values(), key=lambda v: sum(e - b for b, e in v)))
+    kern = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                  for r in csv.DictReader(open(kernel_csv)) if "k_mttkrp" in r["Kernel_Name"])
+    ncalls = len(copies) // per_call_copies
+    lines = [f"# {title}", f"# command: {command}",
+             f"# {len(copies)} chunk copies on the library's copy stream, {len(kern)} MTTKRP "
+             f"kernels, {per_call_copies} copies per call",
+             "# call | copies | kernels | t_copy ms | t_comp ms | t_total ms | overlap"]
+    for c in range(ncalls):
+        grp = copies[c * per_call_copies:(c + 1) * per_call_copies]
+        lo = grp[0][0]
+        hi = copies[(c + 1) * per_call_copies][0] if c + 1 < ncalls else float("inf")
+        ks = [k for k in kern if lo <= k[0] < hi]
+        tc = sum(e - b for b, e in grp) / 1e6
+        tk = sum(e - b for b, e in ks) / 1e6
+        tt = (max([e for _, e in grp] + [e for _, e in ks]) - lo) / 1e6
+        ov = (tc + tk - tt) / min(tc, tk) if ks else float("nan")
+        lines.append(f"{c} | {len(grp)} | {len(ks)} | {tc:.1f} | {tk:.1f} | {tt:.1f} | {ov:.3f}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 # --------------------------------------------------------------------------- helpers
 
 def win_kernel_name(R, N, ft="float", big=False, stash=True):
@@ -454,6 +491,7 @@ def leg_inmemory(args, torch, blco, synth, w, *, check=True, cpu=False, gpu_buil
 
         rng = np.random.default_rng(7)
         errs = {}
+        v64 = vals.astype(np.float64)   # the threaded row oracle takes fp64 values
         for R in w.ranks:
             if R in keep:
                 A, F32, BF16, outs = keep[R]
@@ -467,8 +505,8 @@ def leg_inmemory(args, torch, blco, synth, w, *, check=True, cpu=False, gpu_buil
             for n in modes:
                 rows = check_rows_for(counts[n], w.dims[n], rng)
                 ridx = torch.from_numpy(rows.astype(np.int64)).to(dev)
-                M32, S32 = oracle.mttkrp_rows_f32(coords, vals, A, n, rows, w.dims)
-                Mb, Sb = oracle.mttkrp_rows_f32(coords, vals, Ab, n, rows, w.dims)
+                M32, S32 = oracle.mttkrp_rows_omp(coords, v64, A, n, rows, w.dims)
+                Mb, Sb = oracle.mttkrp_rows_omp(coords, v64, Ab, n, rows, w.dims)
                 g32 = blco.mttkrp(T, n, F32, out=outs[n])[ridx].cpu().numpy().astype(np.float64)
                 gb = blco.mttkrp(T, n, BF16, out=outs[n])[ridx].cpu().numpy().astype(np.float64)
                 for key, got, M, S in (("fp32", g32, M32, S32), ("bf16", gb, Mb, Sb),
@@ -560,11 +598,12 @@ def leg_oom(args, torch, blco, synth, w, *, check=True, cpu=False):
 
         rng = np.random.default_rng(7)
         worst = 0.0
+        v64 = vals.astype(np.float64)   # the threaded row oracle takes fp64 values
         for n in modes:
             o = blco.mttkrp_stream(T, n, F, out=outs[n], device_budget=budget)
             rows = np.unique(np.concatenate([np.arange(8), rng.integers(0, w.dims[n], 24),
                                              [w.dims[n] - 1]])).astype(np.uint32)
-            M, S = oracle.mttkrp_rows_f32(coords, vals, A, n, rows, w.dims)
+            M, S = oracle.mttkrp_rows_omp(coords, v64, A, n, rows, w.dims)
             got = o[torch.from_numpy(rows.astype(np.int64)).to(dev)].cpu().numpy()
             nz = S > 0
             worst = max(worst, float((np.abs(got - M)[nz] / S[nz]).max()))
@@ -818,6 +857,11 @@ def main():
             a, cmds = a[:i], a[i + 1:]
         summarize_counters(a[0], a[1], *a[4:], copy_bytes=int(a[2]), probe_row_ops=int(a[3]),
                            commands=cmds)
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-overlap":
+        # OUT TITLE COPY_CSV KERNEL_CSV COPIES_PER_CALL COMMAND
+        summarize_overlap(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], int(sys.argv[6]),
+                          sys.argv[7])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-stats":
         # OUT TITLE STATS_CSV COMMAND

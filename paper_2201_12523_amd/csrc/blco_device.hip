@@ -271,8 +271,13 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   constexpr int PPG = kWin / G;                 // grouped positions per group (= LPN)
   // positions whose gathers are issued together: BLCO_WIN_U / RPL, except for
   // 3-mode tensors at one or four ranks per lane, where 4 and 1 positions keep
-  // the registers from spilling and measured 8% and 3% faster
-  constexpr int UW = (N == 3 && RPL == 1) ? 4 : (N == 3 && RPL == 4) ? 1 : BLCO_WIN_U / RPL;
+  // the registers from spilling and measured 8% and 3% faster; the fused
+  // residual walk also gathers the target row and keeps the value, the
+  // residual and the position of each, so it takes half as many (at four it
+  // spilled about 45 registers per lane; 4-mode 80M-non-zero CP gradient step
+  // 13.1 -> 12.0 ms)
+  constexpr int UW0 = (N == 3 && RPL == 1) ? 4 : (N == 3 && RPL == 4) ? 1 : BLCO_WIN_U / RPL;
+  constexpr int UW = RES ? (UW0 > 1 ? UW0 / 2 : 1) : UW0;
   constexpr int U = PPG < UW ? PPG : UW;
   // record fields: the other modes' row offsets, target, value; with RES also
   // the target row's offset and the position in the window
