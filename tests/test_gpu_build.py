@@ -107,6 +107,30 @@ def test_edge_cases():
          hot_min_count=1)
 
 
+@pytest.mark.parametrize("nnz", [4095, 4096, 4097, 8192, 3 * 4096 + 1])
+def test_sort_tile_boundaries(nnz):
+    # the radix sort works on tiles of 4096 keys: full, partial and single-key last tiles
+    rng = np.random.default_rng(nnz)
+    dims = (300, 200, 100)
+    coords = rand_coords(rng, dims, nnz)
+    coords[0][: nnz // 5] = 7                  # duplicates: stable order decides
+    coords[1][: nnz // 5] = 9
+    same(coords, rng.standard_normal(nnz).astype(np.float32), dims)
+
+
+@pytest.mark.parametrize("span", [1, 8, 256, 1 << 20])
+def test_sort_skips_constant_digits(span):
+    # only mode 1 varies (its bits sit at index positions 0, 3, 6, 7, 8, ...): 0, 1, 2 or 3
+    # of the index's 8-bit digits change between keys, so the sort runs that many passes
+    # (none: a copy) and skips the others
+    rng = np.random.default_rng(span)
+    dims = (1 << 20, 4, 4)
+    nnz = 20_000
+    coords = [rng.integers(0, span, size=nnz).astype(np.uint32),
+              np.zeros(nnz, np.uint32), np.zeros(nnz, np.uint32)]
+    same(coords, rng.standard_normal(nnz).astype(np.float32), dims)
+
+
 def test_errors_and_pinned_placement():
     rng = np.random.default_rng(6)
     dims = (20, 30, 40)
