@@ -297,8 +297,10 @@ def win_kernel_name(R, N, ft="float", big=False, stash=True):
     (stash: the mode's frequent rows are held in LDS)."""
     lpn, rpl = (16, 1) if R <= 16 else (16, 2) if R <= 32 else (16, 4) if R <= 64 else (64, 2)
     b = lambda v: "true" if v else "false"
-    # the last template argument selects the fused CP-gradient walk, never the plain MTTKRP
-    return f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {b(big)}, {b(stash)}, false>"
+    # then: the fused CP-gradient walk (never for the plain MTTKRP), and vector gathers of
+    # packed bf16 ranks (bf16 factors, two or more ranks per lane, even R)
+    vec = ft != "float" and rpl > 1 and R % 2 == 0
+    return f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {b(big)}, {b(stash)}, false, {b(vec)}>"
 
 
 def short_kernel_name(R, N, ft="float", big=False):

@@ -38,10 +38,14 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_kernel_names(bench):
-    assert bench.win_kernel_name(32, 3) == "k_mttkrp_win<16, 2, float, 3, false, true, false>"
+    assert bench.win_kernel_name(32, 3) == "k_mttkrp_win<16, 2, float, 3, false, true, false, false>"
     assert bench.win_kernel_name(16, 4, "uint16_t", False, False) == \
-        "k_mttkrp_win<16, 1, uint16_t, 4, false, false, false>"
-    assert bench.win_kernel_name(64, 3, big=True) == "k_mttkrp_win<16, 4, float, 3, true, true, false>"
+        "k_mttkrp_win<16, 1, uint16_t, 4, false, false, false, false>"
+    assert bench.win_kernel_name(64, 3, big=True) == "k_mttkrp_win<16, 4, float, 3, true, true, false, false>"
+    assert bench.win_kernel_name(32, 4, "unsigned short") == \
+        "k_mttkrp_win<16, 2, unsigned short, 4, false, true, false, true>"
+    assert bench.win_kernel_name(33, 4, "unsigned short") == \
+        "k_mttkrp_win<16, 4, unsigned short, 4, false, true, false, false>"
     assert bench.short_kernel_name(32, 4) == "k_mttkrp_short<2, float, 4, false>"
 
 
@@ -55,7 +59,7 @@ def test_kernel_names_exist_in_the_library(bench):
     for line in syms.splitlines():
         if line.endswith("(blco::KParams)") or line.endswith("(blco::KParams, long)"):
             names.add(line.split(" ", 2)[2].removeprefix("void ").split("(")[0])
-    for R in (16, 32, 64):
+    for R in (16, 32, 33, 64):
         for N in (3, 4):
             for ft in ("float", "unsigned short"):
                 for stash in (True, False):

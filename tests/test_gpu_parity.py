@@ -138,7 +138,8 @@ def test_ranks(R):
     nnz = 3001
     coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
     vals = rng.random(nnz).astype(np.float32)
-    run_case(coords, vals, dims, R, seed=R, label=f"rank{R}")
+    # bf16 too: odd ranks gather packed bf16 runs with 2-byte loads, even ones with 4/8-byte
+    run_case(coords, vals, dims, R, seed=R, label=f"rank{R}", dtypes=("fp32", "bf16"))
 
 
 @pytest.mark.parametrize("N", [1, 2, 4, 5, 6, 7, 8])
