@@ -290,6 +290,75 @@ def summarize_overlap(out, title, copy_csv, kernel_csv, per_call_copies, command
     print("\n".join(lines))
 
 
+
+def _roofline_text(r):
+    if not r:
+        return "n/a"
+    if r.get("bound") == "pcie":
+        return f"bound by the host link: {r['achieved']:.1f} GB/s host-to-device"
+    s = (f"dominant kernel `{r['kernel']}` (modes {r['modes']}): {r['avg_kernel_ms']:.3f} ms, "
+         f"compulsory {r['algorithmic_bytes_per_launch'] / 1e9:.2f} GB per launch = "
+         f"{r['achieved']:.0f} GB/s = {r['frac']:.3f} of 8 TB/s")
+    if r.get("traffic"):
+        s += (f"; counter traffic {r['traffic'] / 1e9:.2f} GB per launch "
+              f"({r['traffic_over_algorithmic']:.1f}x)")
+    else:
+        s += "; counter traffic null (no counter summary for this kernel source)"
+    a = r.get("atomics") or {}
+    if a.get("frac") is not None:
+        s += (f"; atomic row-updates {a['row_ops_per_launch'] / 1e6:.1f}M = {a['frac']:.2f} of "
+              f"the time at the probe's rate")
+    return s
+
+
+def summarize_bench(out, title, json_path, command):
+    """Markdown form of one bench.py JSON line (the last line of json_path): the headline
+    leg, its per-configuration figures, errors and CPU baseline, then every secondary leg."""
+    d = json.loads(open(json_path).read().strip().splitlines()[-1])
+    md = [f"# bench.py, {title} (MI355X, one GPU)", "", "Command (GPU box, repository root):", "",
+          f"    {command}", "", f"* workload: {d['config']['workload']}",
+          f"* value: {d['value']:.3f} {d['unit']} ({d['metric']}); {d['ms_per_step']:.3f} ms per step"]
+
+    def legs(v, full):
+        o = []
+        if "roofline" in v:
+            o.append(f"* roofline: {_roofline_text(v['roofline'])}")
+        for k, c in v.get("per_config", {}).items():
+            o.append(f"* {k}: {c['ms_per_step']:.3f} ms per step ({c['gnnz_s']:.2f} Gnnz/s), kernel "
+                     f"ms per mode {[round(x, 3) for x in c['kernel_ms']]}"
+                     + (f", resolution {c['resolution']}" if full and "resolution" in c else ""))
+        if "per_storage" in v:
+            o.append("* " + ", ".join(f"{k}: {c['ms_per_step']:.3f} ms per step"
+                                      for k, c in v["per_storage"].items()))
+        for pm in v.get("per_mode", []):
+            o.append(f"* mode {pm['mode'] + 1}: {pm['call_ms']:.1f} ms per call, copy "
+                     f"{pm['copy_ms']:.1f} ms, kernels {pm['kernel_ms']:.1f} ms, host-to-device "
+                     f"{pm['h2d_gbs']:.1f} GB/s, overlap {pm['overlap']:.3f}, {pm['chunks']} chunks")
+        if "one_pass" in v:
+            o.append(f"* every mode per chunk: {json.dumps(v['one_pass'])}")
+        if "errors" in v:
+            o.append("* max normalised error vs the fp64 oracle: " +
+                     ", ".join(f"{k} {e['max']:.2e}" for k, e in v["errors"].items()))
+        return o
+
+    md += legs(d, True)
+    c = d.get("cpu_baseline")
+    if c:
+        md.append(f"* cpu baseline: {c['value']:.5f} {c['unit']} on {c['cores']} cores "
+                  f"({c['sample']}); one thread {c['single_thread']['value']:.5f}")
+    if "build_s" in d:
+        md.append(f"* construction of the headline tensor: host builder {d['build_s']:.2f} s, GPU "
+                  f"builder {d['build_gpu_s'] * 1e3:.1f} ms; wall time of the whole run "
+                  f"{d['wall_s']:.0f} s")
+    for k, v in d.get("secondary", {}).items():
+        md += ["", f"## secondary: {k}", f"* {v.get('config', {}).get('workload', '')}",
+               f"* value: {v['value']:.3f} {v['unit']}; {v['ms_per_step']:.3f} ms per step"]
+        md += legs(v, False)
+    with open(out, "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 # --------------------------------------------------------------------------- helpers
 
 def win_kernel_name(R, N, ft="float", big=False, stash=True):
@@ -864,6 +933,10 @@ def main():
         # OUT TITLE COPY_CSV KERNEL_CSV COPIES_PER_CALL COMMAND
         summarize_overlap(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], int(sys.argv[6]),
                           sys.argv[7])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-bench":
+        # OUT TITLE JSON COMMAND
+        summarize_bench(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-stats":
         # OUT TITLE STATS_CSV COMMAND
