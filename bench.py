@@ -366,10 +366,13 @@ def win_kernel_name(R, N, ft="float", big=False, stash=True):
     (stash: the mode's frequent rows are held in LDS)."""
     lpn, rpl = (16, 1) if R <= 16 else (16, 2) if R <= 32 else (16, 4) if R <= 64 else (64, 2)
     b = lambda v: "true" if v else "false"
-    # then: the fused CP-gradient walk (never for the plain MTTKRP), and vector gathers of
-    # packed bf16 ranks (bf16 factors, two or more ranks per lane, even R)
+    # then: the fused CP-gradient walk (never for the plain MTTKRP), vector gathers of
+    # packed bf16 ranks (bf16 factors, two or more ranks per lane, even R), and the
+    # non-zeros per thread (two without a stash at R <= 64 and at most 5 modes)
     vec = ft != "float" and rpl > 1 and R % 2 == 0
-    return f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {b(big)}, {b(stash)}, false, {b(vec)}>"
+    wpt = 2 if (not stash and lpn == 16 and N <= 5) else 1
+    return (f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {b(big)}, {b(stash)}, false, {b(vec)}, "
+            f"{wpt}>")
 
 
 def short_kernel_name(R, N, ft="float", big=False):

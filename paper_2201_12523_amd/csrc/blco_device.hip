@@ -313,11 +313,21 @@ __device__ __forceinline__ int hot_lookup(const uint32_t* keys, const uint32_t* 
 // xhat_k = sum_r prod_m A^(m)[i_m^k, r] (a sum over the 16 lanes of the group),
 // the residual e_k = x_k - xhat_k, which it writes to p.resid in BLCO order, and
 // sums e_k * prod_{m != mode} A^(m) instead of x_k * prod_{m != mode} A^(m).
+//
+// WPT: non-zeros per thread, so a window holds kWin * WPT non-zeros.  Two (for modes
+// without a stash) merge more terms per flush: on the 2^20-row and 1024-row modes of
+// the 4-mode 200M-non-zero tensor, 16% and 32% fewer row flushes than at one.
 template <int LPN, int RPL, typename FT, int N, bool BIG, bool STASH, bool RES = false,
-          bool VEC = false>
+          bool VEC = false, int WPT = 1>
 __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
+  constexpr int W = kWin * WPT;                 // non-zeros per window
   constexpr int G = kWin / LPN;                 // groups of LPN lanes
-  constexpr int PPG = kWin / G;                 // grouped positions per group (= LPN)
+  constexpr int PPG = W / G;                    // grouped positions per group (= LPN * WPT)
+  static_assert(PPG <= 64, "a group's segment ends must fit one 64-bit word");
+  static_assert(WPT == 1 || (!STASH && !RES), "multi-non-zero windows: plain MTTKRP, no stash");
+  // hash buckets: 4096 per 1024 non-zeros, 6144 per 2048 (two workgroups per CU keep
+  // fitting in LDS)
+  constexpr int NB = WPT == 1 ? kBuckets : kBuckets * 3 / 2;
   // positions whose gathers are issued together: BLCO_WIN_U / RPL, except for
   // 3-mode tensors at one or four ranks per lane, where 4 and 1 positions keep
   // the registers from spilling and measured 8% and 3% faster; the fused
@@ -339,11 +349,11 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   // loads measured faster than 8- and 16-byte ones
   constexpr bool PACKED = sizeof(FT) == 2 && RPL > 1;
   static_assert(!VEC || PACKED, "vector gathers are for packed bf16 ranks");
-  __shared__ __align__(16) uint32_t s_rec[kWin * NP];  // records by grouped position
-  __shared__ uint64_t s_end[kWin / 64];
+  __shared__ __align__(16) uint32_t s_rec[W * NP];  // records by grouped position
+  __shared__ uint64_t s_end[W / 64];
   // the histogram (processing) and the carry partial sums (computing) are never
   // live at once: they share one array
-  constexpr int NHH = kBuckets > kWin * RPL ? kBuckets : kWin * RPL;
+  constexpr int NHH = NB > kWin * RPL ? NB : kWin * RPL;
   __shared__ __align__(16) uint32_t s_hist[NHH];
   float* s_head = reinterpret_cast<float*>(s_hist);
   __shared__ uint32_t s_wsum[kWin / 64];
@@ -356,7 +366,7 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   uint32_t* s_hidx = s_hkey + kHotSlots;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int64_t nwin = (p.n + kWin - 1) / kWin;
+  const int64_t nwin = (p.n + W - 1) / W;
   if (K > 0) {
     for (int i = tid; i < K * R; i += kWin) s_stash[i] = 0.f;
     for (int i = tid; i < kHotSlots; i += kWin) s_hkey[i] = kNoRow;
@@ -375,14 +385,17 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   }
   // windows of this workgroup: blockIdx.x, blockIdx.x + gridDim.x, ...
   const int64_t wstep = gridDim.x;
-  // the first window's non-zero of this thread
-  uint64_t nkey = 0;
-  float nx = 0.f;
-  {
-    const int64_t k = (int64_t)blockIdx.x * kWin + tid;
+  // the first window's non-zeros of this thread: window positions tid + i * kWin
+  uint64_t nkey[WPT];
+  float nx[WPT];
+#pragma unroll
+  for (int i = 0; i < WPT; ++i) {
+    nkey[i] = 0;
+    nx[i] = 0.f;
+    const int64_t k = (int64_t)blockIdx.x * W + tid + i * kWin;
     if ((int64_t)blockIdx.x < nwin && k < p.n) {
-      nkey = p.keys[k];
-      nx = p.vals[k];
+      nkey[i] = p.keys[k];
+      nx[i] = p.vals[k];
     }
   }
   constexpr int NO = N > 1 ? N - 1 : 1;          // other modes
@@ -406,70 +419,84 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   const uint64_t gmask = PPG >= 64 ? ~0ULL : ((1ULL << PPG) - 1);
 
   for (int64_t win = blockIdx.x; win < nwin; win += wstep) {
-    const int64_t k0 = win * kWin;
-    const int nvalid = (int)min((int64_t)kWin, p.n - k0);
-    const bool valid = tid < nvalid;
+    const int64_t k0 = win * W;
+    const int nvalid = (int)min((int64_t)W, p.n - k0);
 
     // ---- processing: decode, group by target
-    uint32_t c[N];
-    const float x = valid ? nx : 0.f;
-    if (valid) {
-      decode<N>(p, nkey, p.base + k0 + tid, c);
-    } else {
+    uint32_t c[WPT][N], tgt[WPT], tfield[WPT], bkt[WPT], rank[WPT];
 #pragma unroll
-      for (int m = 0; m < N; ++m) c[m] = 0;
+    for (int i = 0; i < WPT; ++i) {
+      const int wp = tid + i * kWin;   // position in the window
+      if (wp < nvalid) {
+        decode<N>(p, nkey[i], p.base + k0 + wp, c[i]);
+      } else {
+#pragma unroll
+        for (int m = 0; m < N; ++m) c[i][m] = 0;
+      }
+      tgt[i] = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m)
+        if (m == p.mode) tgt[i] = c[i][m];
     }
-    uint32_t tgt = 0;
-#pragma unroll
-    for (int m = 0; m < N; ++m)
-      if (m == p.mode) tgt = c[m];
-    for (int i = tid; i < kBuckets; i += kWin) s_hist[i] = 0;
+    for (int i = tid; i < NB; i += kWin) s_hist[i] = 0;
     __syncthreads();   // also: the stash lookup is built, the previous window is done
     // counting sort on a hash of the target; a frequent row has bucket = its
     // stash index, the other targets share the remaining buckets (two targets
     // sharing a bucket may interleave, which only splits a segment)
-    uint32_t tfield = tgt, bkt;
-    const int hs = (K > 0 && valid) ? hot_lookup(s_hkey, s_hidx, tgt) : -1;
-    if (hs >= 0) {
-      bkt = (uint32_t)hs;
-      tfield = kHotFlag | (uint32_t)hs;
-    } else {
-      const uint32_t h = tgt * 0x9E3779B1u;
-      bkt = (uint32_t)K + (uint32_t)(((uint64_t)h * (uint32_t)(kBuckets - K)) >> 32);
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const bool valid = tid + i * kWin < nvalid;
+      tfield[i] = tgt[i];
+      const int hs = (K > 0 && valid) ? hot_lookup(s_hkey, s_hidx, tgt[i]) : -1;
+      if (hs >= 0) {
+        bkt[i] = (uint32_t)hs;
+        tfield[i] = kHotFlag | (uint32_t)hs;
+      } else {
+        const uint32_t h = tgt[i] * 0x9E3779B1u;
+        bkt[i] = (uint32_t)K + (uint32_t)(((uint64_t)h * (uint32_t)(NB - K)) >> 32);
+      }
+      rank[i] = valid ? atomicAdd(&s_hist[bkt[i]], 1u) : 0u;
     }
-    uint32_t rank = 0;
-    if (valid) rank = atomicAdd(&s_hist[bkt], 1u);
     __syncthreads();
-    block_exclusive_scan<kBuckets, kWin>(s_hist, tid, s_wsum);
+    block_exclusive_scan<NB, kWin>(s_hist, tid, s_wsum);
     // record at the grouped position: fields 0..N-2 the byte offsets (row
     // indices when BIG) of the other modes' factor rows in ascending mode
-    // order, field N-1 the target field, field N the value; padding lanes
-    // keep their own (trailing) positions
-    const int pos = valid ? (int)(s_hist[bkt] + rank) : tid;
+    // order, field N-1 the target field, field N the value; padding positions
+    // (nvalid and above) stay where they are
 #pragma unroll
-    for (int j = 0; j + 1 < N; ++j) {
-      const uint32_t cj = (j < p.mode) ? c[j] : c[j + 1];
-      s_rec[pos * NP + j] = BIG ? cj : cj * p.rowbytes;
-    }
-    s_rec[pos * NP + N - 1] = tfield;
-    s_rec[pos * NP + N] = __float_as_uint(x);
-    if constexpr (RES) {
-      s_rec[pos * NP + N + 1] = tgt * p.rowbytes;
-      s_rec[pos * NP + N + 2] = (uint32_t)tid;
+    for (int i = 0; i < WPT; ++i) {
+      const int wp = tid + i * kWin;
+      const int pos = wp < nvalid ? (int)(s_hist[bkt[i]] + rank[i]) : wp;
+#pragma unroll
+      for (int j = 0; j + 1 < N; ++j) {
+        const uint32_t cj = (j < p.mode) ? c[i][j] : c[i][j + 1];
+        s_rec[pos * NP + j] = BIG ? cj : cj * p.rowbytes;
+      }
+      s_rec[pos * NP + N - 1] = tfield[i];
+      s_rec[pos * NP + N] = __float_as_uint(wp < nvalid ? nx[i] : 0.f);
+      if constexpr (RES) {
+        s_rec[pos * NP + N + 1] = tgt[i] * p.rowbytes;
+        s_rec[pos * NP + N + 2] = (uint32_t)wp;
+      }
     }
     __syncthreads();
-    {
-      const uint32_t t0 = s_rec[tid * NP + N - 1];
-      const bool end = (tid < nvalid) && (tid == nvalid - 1 || s_rec[(tid + 1) * NP + N - 1] != t0);
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int wp = tid + i * kWin;
+      const uint32_t t0 = s_rec[wp * NP + N - 1];
+      const bool end = (wp < nvalid) && (wp == nvalid - 1 || s_rec[(wp + 1) * NP + N - 1] != t0);
       const uint64_t em = __ballot(end);
-      if (lane == 0) s_end[tid >> 6] = em;
+      if (lane == 0) s_end[wp >> 6] = em;
     }
-    // the next window's non-zero, in flight during this walk
+    // the next window's non-zeros, in flight during this walk
     if constexpr (STASH) {
-      const int64_t k = (win + wstep) * kWin + tid;
-      if (win + wstep < nwin && k < p.n) {
-        nkey = p.keys[k];
-        nx = p.vals[k];
+#pragma unroll
+      for (int i = 0; i < WPT; ++i) {
+        const int64_t k = (win + wstep) * W + tid + i * kWin;
+        if (win + wstep < nwin && k < p.n) {
+          nkey[i] = p.keys[k];
+          nx[i] = p.vals[k];
+        }
       }
     }
     __syncthreads();
@@ -489,10 +516,6 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
     constexpr bool kRowB = (LPN == 16) && (N == 3);
     for (int r0 = 0; r0 < R; r0 += LPN * RPL) {
       uint32_t myrec[kRowB ? NF : 1];
-      if constexpr (kRowB) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) myrec[f] = s_rec[(p0 + rl) * NP + f];
-      }
       bool ract[RPL];
       uint32_t loff[RPL];
       float acc[RPL], carry[RPL];
@@ -506,6 +529,13 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
       }
       bool first = true, has_carry = false;
       for (int q0 = 0; q0 < PPG; q0 += U) {
+        if constexpr (kRowB) {
+          // the records of the next LPN positions, one per lane
+          if (q0 % LPN == 0) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) myrec[f] = s_rec[(p0 + q0 + rl) * NP + f];
+          }
+        }
         float pr[U][RPL];
         float ta[RES ? U : 1][RPL];
         float xs[RES ? U : 1];
@@ -1066,15 +1096,40 @@ static KernelFn pick_win_s(int N) {
   }
 }
 
+// windows of 2048 non-zeros (two per thread; no stash), up to 5 modes
+constexpr int kWideMaxN = 5;
+template <int LPN, int RPL, typename FT, bool BIG, bool VEC>
+static KernelFn pick_win_wide(int N) {
+  switch (N) {
+    case 1: return k_mttkrp_win<LPN, RPL, FT, 1, BIG, false, false, VEC, 2>;
+    case 2: return k_mttkrp_win<LPN, RPL, FT, 2, BIG, false, false, VEC, 2>;
+    case 3: return k_mttkrp_win<LPN, RPL, FT, 3, BIG, false, false, VEC, 2>;
+    case 4: return k_mttkrp_win<LPN, RPL, FT, 4, BIG, false, false, VEC, 2>;
+    default: return k_mttkrp_win<LPN, RPL, FT, 5, BIG, false, false, VEC, 2>;
+  }
+}
+
+// Non-zeros per thread of the window kernel: two for a plain MTTKRP without a stash
+// over 16-lane groups (R <= 64) and at most kWideMaxN modes, else one.
+static int win_wpt(int N, int R, bool stash, bool resid) {
+  return (!stash && !resid && R <= 64 && N <= kWideMaxN) ? 2 : 1;
+}
+
 // VEC (vector gathers of packed bf16 ranks) only where the ranks are packed: bf16
 // factors, two or more ranks per lane, and an even R
 template <int LPN, int RPL, typename FT, bool BIG>
 static KernelFn pick_win(int N, int R, bool stash) {
+  const bool wide = win_wpt(N, R, stash, false) == 2;
   if constexpr (sizeof(FT) == 2 && RPL > 1) {
-    if (R % 2 == 0)
+    if (R % 2 == 0) {
+      if constexpr (LPN == 16)
+        if (wide) return pick_win_wide<LPN, RPL, FT, BIG, true>(N);
       return stash ? pick_win_s<LPN, RPL, FT, BIG, true, true>(N)
                    : pick_win_s<LPN, RPL, FT, BIG, false, true>(N);
+    }
   }
+  if constexpr (LPN == 16)
+    if (wide) return pick_win_wide<LPN, RPL, FT, BIG, false>(N);
   return stash ? pick_win_s<LPN, RPL, FT, BIG, true, false>(N)
                : pick_win_s<LPN, RPL, FT, BIG, false, false>(N);
 }
@@ -1397,11 +1452,12 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
   {
     const int N = t->lay.N;
     KernelFn f = resid ? select_res(N, rank, fdt, true) : select_win(N, rank, fdt, big, true);
-    const int64_t nwin = (n + kWin - 1) / kWin;
     const int K = stash_rows(t, mode, rank, f);
     p.hot = t->d_hot + (size_t)mode * kHotMax;
     p.nhot = K;
     if (K == 0) f = resid ? select_res(N, rank, fdt, false) : select_win(N, rank, fdt, big, false);
+    const int64_t nwin = (n + (int64_t)kWin * win_wpt(N, rank, K > 0, resid) - 1) /
+                         ((int64_t)kWin * win_wpt(N, rank, K > 0, resid));
     const size_t dyn = K > 0 ? (size_t)K * rank * 4 + 2 * (size_t)kHotSlots * 4 : 0;
     // with a stash: persistent workgroups, kWinRounds times the resident count
     // (two per CU), which balances the end of the launch (measured 1-2% faster

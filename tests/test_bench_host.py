@@ -38,14 +38,19 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_kernel_names(bench):
-    assert bench.win_kernel_name(32, 3) == "k_mttkrp_win<16, 2, float, 3, false, true, false, false>"
+    assert bench.win_kernel_name(32, 3) == "k_mttkrp_win<16, 2, float, 3, false, true, false, false, 1>"
     assert bench.win_kernel_name(16, 4, "uint16_t", False, False) == \
-        "k_mttkrp_win<16, 1, uint16_t, 4, false, false, false, false>"
-    assert bench.win_kernel_name(64, 3, big=True) == "k_mttkrp_win<16, 4, float, 3, true, true, false, false>"
+        "k_mttkrp_win<16, 1, uint16_t, 4, false, false, false, false, 2>"
+    assert bench.win_kernel_name(64, 3, big=True) == \
+        "k_mttkrp_win<16, 4, float, 3, true, true, false, false, 1>"
     assert bench.win_kernel_name(32, 4, "unsigned short") == \
-        "k_mttkrp_win<16, 2, unsigned short, 4, false, true, false, true>"
+        "k_mttkrp_win<16, 2, unsigned short, 4, false, true, false, true, 1>"
     assert bench.win_kernel_name(33, 4, "unsigned short") == \
-        "k_mttkrp_win<16, 4, unsigned short, 4, false, true, false, false>"
+        "k_mttkrp_win<16, 4, unsigned short, 4, false, true, false, false, 1>"
+    assert bench.win_kernel_name(32, 6, stash=False) == \
+        "k_mttkrp_win<16, 2, float, 6, false, false, false, false, 1>"
+    assert bench.win_kernel_name(100, 4, stash=False) == \
+        "k_mttkrp_win<64, 2, float, 4, false, false, false, false, 1>"
     assert bench.short_kernel_name(32, 4) == "k_mttkrp_short<2, float, 4, false>"
 
 
@@ -59,8 +64,8 @@ def test_kernel_names_exist_in_the_library(bench):
     for line in syms.splitlines():
         if line.endswith("(blco::KParams)") or line.endswith("(blco::KParams, long)"):
             names.add(line.split(" ", 2)[2].removeprefix("void ").split("(")[0])
-    for R in (16, 32, 33, 64):
-        for N in (3, 4):
+    for R in (16, 32, 33, 64, 100):
+        for N in (3, 4, 6):
             for ft in ("float", "unsigned short"):
                 for stash in (True, False):
                     assert bench.win_kernel_name(R, N, ft, False, stash) in names

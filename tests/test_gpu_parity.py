@@ -152,6 +152,20 @@ def test_mode_counts(N):
     run_case(coords, vals, dims, 8, seed=N, label=f"N{N}")
 
 
+@pytest.mark.parametrize("N", [3, 4])
+@pytest.mark.parametrize("nnz", [1023, 1025, 2047, 2048, 2049, 4095, 6145])
+def test_window_boundaries(nnz, N):
+    """Non-zero counts around the 1024- and 2048-non-zero windows (modes without a
+    stash take two non-zeros per thread): a 7-row mode whose segments run across many
+    lane groups, a 5000-row mode with short ones, and the stash path beside them."""
+    rng = np.random.default_rng(nnz * 10 + N)
+    dims = (7, 300, 5000, 3)[:N]
+    coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
+    vals = rng.standard_normal(nnz).astype(np.float32)
+    run_case(coords, vals, dims, 32, seed=nnz, label=f"win{nnz}N{N}", dtypes=("fp32", "bf16"),
+             resolutions=("register", "frequent"))
+
+
 @pytest.mark.parametrize("pattern", ["one_row", "distinct", "lane_mod_3", "tail_65", "tail_1"])
 def test_conflict_patterns(pattern):
     rng = np.random.default_rng(7)
