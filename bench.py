@@ -60,10 +60,17 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """First 16 hex digits of the SHA-256 of the kernel sources' code: comments, blank
+    lines and trailing blanks are removed first, so a summary of counters taken on a
+    kernel stays valid across edits of its comments, and no longer after any other."""
+    import re
+
     h = hashlib.sha256()
     for f in ("blco_device.hip", "blco_kernels.h"):
-        with open(os.path.join(ROOT, "paper_2201_12523_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2201_12523_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()[:16]
 
 

@@ -5,8 +5,9 @@
 // computing split of Section 5.1 (Figure 7), re-designed for wave64 and the
 // memory-side atomics of MI355X:
 //   k_mttkrp_win (register-based resolution, Section 5.2): one 1024-thread
-//     workgroup per window of 1024 consecutive non-zeros.  Processing: each
-//     thread loads one (key, value) pair (coalesced), decodes the coordinates
+//     workgroup per window of 1024 consecutive non-zeros (2048 on modes without
+//     frequent rows).  Processing: each
+//     thread loads one or two (key, value) pairs (coalesced), decodes the coordinates
 //     by shift and mask (Figure 6b), and the window is grouped by target row
 //     with a counting sort on a hash of the target (LDS histogram, workgroup
 //     scan, scatter), so each target forms one segment; every grouped position
@@ -284,9 +285,9 @@ __device__ __forceinline__ int hot_lookup(const uint32_t* keys, const uint32_t* 
 }
 
 // BLCO MTTKRP with register-based conflict resolution (Sections 5.1-5.2) over
-// windows of 1024 consecutive non-zeros; persistent workgroups take windows
+// windows of 1024 * WPT consecutive non-zeros; persistent workgroups take windows
 // in turn (see below)
-//   processing: one non-zero per thread is loaded (the next window's load is
+//   processing: WPT non-zeros per thread are loaded (the next window's load is
 //     issued before the current walk) and decoded by shift and mask; the
 //     window is grouped by target with a counting sort (LDS histogram with
 //     atomic ranks, exclusive scan, scatter) on a hash of the target, so each
