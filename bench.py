@@ -51,7 +51,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MTTKRP Gnnz/s per mode & % HBM peak; bf16 vs fp32 factors at stated rel error"
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_mttkrp_zipf4.txt")
+def counters_file(workload):
+    """The committed rocprofv3 counter summary of a workload's MTTKRP kernels."""
+    return os.path.join(ROOT, "profiles", f"counters_mttkrp_{workload}.txt")
+
+
+COUNTERS_FILE = counters_file("zipf4")
 T_START = time.time()
 
 
@@ -349,6 +354,12 @@ def summarize_bench(out, title, json_path, command):
         return o
 
     md += legs(d, True)
+    for k in ("mttkrp_kernel_ms", "mttkrp_share_of_iteration", "fits", "pinv_fallbacks"):
+        if k in d:
+            v = d[k]
+            v = [round(x, 4) for x in v] if isinstance(v, list) else (
+                round(v, 4) if isinstance(v, float) else v)
+            md.append(f"* {k}: {v}")
     c = d.get("cpu_baseline")
     if c:
         md.append(f"* cpu baseline: {c['value']:.5f} {c['unit']} on {c['cores']} cores "
@@ -383,9 +394,12 @@ def win_kernel_name(R, N, ft="float", big=False, stash=True):
 
 
 def short_kernel_name(R, N, ft="float", big=False):
-    """Template name of the hierarchical MTTKRP kernel for a single rank slice of width R."""
+    """Template name of the hierarchical MTTKRP kernel for a single rank slice of width R
+    (vector gathers of packed bf16 ranks: bf16, two or more ranks per lane, even R)."""
     rpl = 1 if R <= 16 else 2 if R <= 32 else 4
-    return f"k_mttkrp_short<{rpl}, {ft}, {N}, {'true' if big else 'false'}>"
+    vec = ft != "float" and rpl > 1 and R % 2 == 0 and not big
+    b = lambda v: "true" if v else "false"
+    return f"k_mttkrp_short<{rpl}, {ft}, {N}, {b(big)}, {b(vec)}>"
 
 
 def big_factors(dims, R, sf, n):
@@ -538,7 +552,7 @@ def leg_inmemory(args, torch, blco, synth, w, *, check=True, cpu=False, gpu_buil
     avg_ms = float(np.mean([head["kernel_ms"][n] for n in dm]))
     alg = float(np.mean([head["compulsory_bytes"][n] for n in dm]))
     achieved = alg / (avg_ms * 1e-3) / 1e9
-    counters = read_counters() if (w.name == "zipf4" and args.nnz is None) else None
+    counters = read_counters(counters_file(w.name)) if args.nnz is None else None
     traffic = counter_traffic(counters, dom)
     calib = atomic_calibration(torch, blco, R, args.steps)
     rops = counter_row_ops(counters, dom)

@@ -727,10 +727,15 @@ __host__ __device__ constexpr size_t short_fixed_lds(int N, int cls) {
          (size_t)kShortNG * cls * 4;
 }
 
-template <int RPL, typename FT, int N, bool BIG>
+//
+// Rank layout as in the window kernel: with bf16 factors each lane holds RPL
+// consecutive ranks of the slice (VEC: one 4- or 8-byte gather when R is even).
+template <int RPL, typename FT, int N, bool BIG, bool VEC = false>
 __global__ __launch_bounds__(kShortB, 8) void k_mttkrp_short(KParams p, int64_t per) {
   extern __shared__ __align__(16) unsigned char smem_short[];
   constexpr int LPN = kShortLPN;
+  constexpr bool PACKED = sizeof(FT) == 2 && RPL > 1;
+  static_assert(!VEC || PACKED, "vector gathers are for packed bf16 ranks");
   constexpr int NF = N + 1;
   constexpr int NG = kShortNG;
   constexpr int C = kShortB / NG;            // positions per group and batch
@@ -764,9 +769,11 @@ __global__ __launch_bounds__(kShortB, 8) void k_mttkrp_short(KParams p, int64_t 
   }
   uint32_t loff[RPL];
   bool ract[RPL];
+  int rix[RPL];   // slice-relative rank of each of this lane's RPL values
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
-    const int r = rl + q * LPN;
+    const int r = PACKED ? rl * RPL + q : rl + q * LPN;
+    rix[q] = r;
     ract[q] = r < W;
     loff[q] = (uint32_t)(rlo + (ract[q] ? r : 0)) * (uint32_t)sizeof(FT);
   }
@@ -830,6 +837,11 @@ __global__ __launch_bounds__(kShortB, 8) void k_mttkrp_short(KParams p, int64_t 
 #pragma unroll
               for (int q = 0; q < RPL; ++q)
                 pr[u][q] *= ld_factor<FT>(rowp, (size_t)(loff[q] / sizeof(FT)));
+            } else if constexpr (PACKED) {
+              float t3[RPL];
+              ld_bf16_run<RPL, VEC>(rs[jj], e[jj] + loff[0], t3);
+#pragma unroll
+              for (int q = 0; q < RPL; ++q) pr[u][q] *= t3[q];
             } else {
 #pragma unroll
               for (int q = 0; q < RPL; ++q) pr[u][q] *= ld_buf<FT>(rs[jj], e[jj] + loff[q]);
@@ -843,11 +855,11 @@ __global__ __launch_bounds__(kShortB, 8) void k_mttkrp_short(KParams p, int64_t 
             // a finished segment that does not reach the end of this group
             if (first && first_shared) {
 #pragma unroll
-              for (int q = 0; q < RPL; ++q) s_carry[gi * CW + rl + q * LPN] = acc[q];
+              for (int q = 0; q < RPL; ++q) s_carry[gi * CW + rix[q]] = acc[q];
             } else {
 #pragma unroll
               for (int q = 0; q < RPL; ++q)
-                if (ract[q]) s_out[cur * SW + rl + q * LPN] += acc[q];
+                if (ract[q]) s_out[cur * SW + rix[q]] += acc[q];
             }
             first = false;
             cur = tg[u];
@@ -861,7 +873,7 @@ __global__ __launch_bounds__(kShortB, 8) void k_mttkrp_short(KParams p, int64_t 
       // the segment that reaches the end of this group
       if (first && first_shared) {
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) s_carry[gi * CW + rl + q * LPN] = acc[q];
+        for (int q = 0; q < RPL; ++q) s_carry[gi * CW + rix[q]] = acc[q];
       } else if (last_cont) {
         pending = true;
         // the scanned histogram holds each target's first position, so the
@@ -870,7 +882,7 @@ __global__ __launch_bounds__(kShortB, 8) void k_mttkrp_short(KParams p, int64_t 
       } else {
 #pragma unroll
         for (int q = 0; q < RPL; ++q)
-          if (ract[q]) s_out[cur * SW + rl + q * LPN] += acc[q];
+          if (ract[q]) s_out[cur * SW + rix[q]] += acc[q];
       }
     }
     __syncthreads();
@@ -879,11 +891,11 @@ __global__ __launch_bounds__(kShortB, 8) void k_mttkrp_short(KParams p, int64_t 
 #pragma unroll 4
       for (int g2 = gi + 1; g2 * C < run_end; ++g2) {
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) acc[q] += s_carry[g2 * CW + rl + q * LPN];
+        for (int q = 0; q < RPL; ++q) acc[q] += s_carry[g2 * CW + rix[q]];
       }
 #pragma unroll
       for (int q = 0; q < RPL; ++q)
-        if (ract[q]) s_out[cur * SW + rl + q * LPN] += acc[q];
+        if (ract[q]) s_out[cur * SW + rix[q]] += acc[q];
     }
     for (int i = tid; i < kShortHist; i += kShortB) s_hist[i] = 0;
   }
@@ -1172,35 +1184,45 @@ static KernelFn select_res(int N, int R, int fdt, bool stash) {
 
 typedef void (*ShortFn)(KParams, int64_t);
 
-template <int RPL, typename FT, bool BIG>
-static ShortFn pick_short(int N) {
+template <int RPL, typename FT, bool BIG, bool VEC>
+static ShortFn pick_short_v(int N) {
   switch (N) {
-    case 1: return k_mttkrp_short<RPL, FT, 1, BIG>;
-    case 2: return k_mttkrp_short<RPL, FT, 2, BIG>;
-    case 3: return k_mttkrp_short<RPL, FT, 3, BIG>;
-    case 4: return k_mttkrp_short<RPL, FT, 4, BIG>;
-    case 5: return k_mttkrp_short<RPL, FT, 5, BIG>;
-    case 6: return k_mttkrp_short<RPL, FT, 6, BIG>;
-    case 7: return k_mttkrp_short<RPL, FT, 7, BIG>;
-    default: return k_mttkrp_short<RPL, FT, 8, BIG>;
+    case 1: return k_mttkrp_short<RPL, FT, 1, BIG, VEC>;
+    case 2: return k_mttkrp_short<RPL, FT, 2, BIG, VEC>;
+    case 3: return k_mttkrp_short<RPL, FT, 3, BIG, VEC>;
+    case 4: return k_mttkrp_short<RPL, FT, 4, BIG, VEC>;
+    case 5: return k_mttkrp_short<RPL, FT, 5, BIG, VEC>;
+    case 6: return k_mttkrp_short<RPL, FT, 6, BIG, VEC>;
+    case 7: return k_mttkrp_short<RPL, FT, 7, BIG, VEC>;
+    default: return k_mttkrp_short<RPL, FT, 8, BIG, VEC>;
   }
+}
+
+// VEC where the bf16 ranks are packed (two or more per lane) and R is even
+template <int RPL, typename FT, bool BIG>
+static ShortFn pick_short(int N, int R) {
+  if constexpr (sizeof(FT) == 2 && RPL > 1 && !BIG) {
+    if (R % 2 == 0) return pick_short_v<RPL, FT, BIG, true>(N);
+  }
+  return pick_short_v<RPL, FT, BIG, false>(N);
 }
 
 // ranks per lane of the hierarchical kernel for a slice width (<= 64)
 static int short_rpl(int SW) { return SW <= 16 ? 1 : SW <= 32 ? 2 : 4; }
 
 template <typename FT, bool BIG>
-static ShortFn select_short_t(int N, int SW) {
+static ShortFn select_short_t(int N, int SW, int R) {
   const int rpl = short_rpl(SW);
-  if (rpl == 1) return pick_short<1, FT, BIG>(N);
-  if (rpl == 2) return pick_short<2, FT, BIG>(N);
-  return pick_short<4, FT, BIG>(N);
+  if (rpl == 1) return pick_short<1, FT, BIG>(N, R);
+  if (rpl == 2) return pick_short<2, FT, BIG>(N, R);
+  return pick_short<4, FT, BIG>(N, R);
 }
 
-static ShortFn select_short(int N, int SW, int fdt, bool big) {
+static ShortFn select_short(int N, int SW, int R, int fdt, bool big) {
   if (fdt == BLCO_F32)
-    return big ? select_short_t<float, true>(N, SW) : select_short_t<float, false>(N, SW);
-  return big ? select_short_t<uint16_t, true>(N, SW) : select_short_t<uint16_t, false>(N, SW);
+    return big ? select_short_t<float, true>(N, SW, R) : select_short_t<float, false>(N, SW, R);
+  return big ? select_short_t<uint16_t, true>(N, SW, R)
+             : select_short_t<uint16_t, false>(N, SW, R);
 }
 
 static size_t short_lds(int N, uint64_t rows, int SW) {
@@ -1445,7 +1467,7 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
     per = (per + kShortB - 1) / kShortB * kShortB;
     const int64_t nwg = (n + per - 1) / per;
     const size_t lds = short_lds(t->lay.N, t->lay.dims[mode], sw);
-    ShortFn f = select_short(t->lay.N, sw, fdt, big);
+    ShortFn f = select_short(t->lay.N, sw, rank, fdt, big);
     hipLaunchKernelGGL(f, dim3((unsigned)nwg, (unsigned)slices), dim3(kShortB), lds, s, p, per);
     HIPCHK(hipGetLastError());
     return BLCO_OK;

@@ -51,7 +51,11 @@ def test_kernel_names(bench):
         "k_mttkrp_win<16, 2, float, 6, false, false, false, false, 1>"
     assert bench.win_kernel_name(100, 4, stash=False) == \
         "k_mttkrp_win<64, 2, float, 4, false, false, false, false, 1>"
-    assert bench.short_kernel_name(32, 4) == "k_mttkrp_short<2, float, 4, false>"
+    assert bench.short_kernel_name(32, 4) == "k_mttkrp_short<2, float, 4, false, false>"
+    assert bench.short_kernel_name(32, 4, "unsigned short") == \
+        "k_mttkrp_short<2, unsigned short, 4, false, true>"
+    assert bench.short_kernel_name(33, 3, "unsigned short") == \
+        "k_mttkrp_short<4, unsigned short, 3, false, false>"
 
 
 def test_kernel_names_exist_in_the_library(bench):

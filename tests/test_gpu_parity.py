@@ -131,7 +131,7 @@ def test_small_workload_all_modes():
         check_entries(out.cpu().numpy(), M, S, label=f"small mode {n}")
 
 
-@pytest.mark.parametrize("R", [1, 3, 16, 32, 33, 64, 100])
+@pytest.mark.parametrize("R", [1, 3, 16, 18, 32, 33, 34, 62, 64, 100])
 def test_ranks(R):
     rng = np.random.default_rng(R)
     dims = (97, 61, 45)
@@ -139,6 +139,7 @@ def test_ranks(R):
     coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
     vals = rng.random(nnz).astype(np.float32)
     # bf16 too: odd ranks gather packed bf16 runs with 2-byte loads, even ones with 4/8-byte
+    # (at R = 34 and 62 the 8-byte runs start 4-byte aligned)
     run_case(coords, vals, dims, R, seed=R, label=f"rank{R}", dtypes=("fp32", "bf16"))
 
 
