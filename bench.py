@@ -216,7 +216,7 @@ def counter_row_ops(counters, kernel):
             "requests": k["TCC_EA0_ATOMIC_sum"]}
 
 
-SUMMARY_KERNELS = ("k_mttkrp", "k_atomic_probe", "k_loss_tile")
+SUMMARY_KERNELS = ("k_mttkrp", "k_atomic_probe", "k_gather_probe", "k_loss_tile")
 
 
 def summarize_counters(out, title, *csvs, copy_bytes=0, probe_row_ops=0, commands=()):
@@ -320,6 +320,11 @@ def _roofline_text(r):
     if a.get("frac") is not None:
         s += (f"; atomic row-updates {a['row_ops_per_launch'] / 1e6:.1f}M = {a['frac']:.2f} of "
               f"the time at the probe's rate")
+    m = r.get("request_model")
+    if m:
+        s += (f"; requests priced at the probes' rates: L2 read misses {m['miss_ms']:.2f} ms + "
+              f"atomics {m['atomic_ms']:.2f} ms = {m['serial_ms']:.2f} ms = {m['frac']:.2f} of the "
+              f"kernel's time")
     return s
 
 
@@ -372,6 +377,29 @@ def summarize_bench(out, title, json_path, command):
         md += ["", f"## secondary: {k}", f"* {v.get('config', {}).get('workload', '')}",
                f"* value: {v['value']:.3f} {v['unit']}; {v['ms_per_step']:.3f} ms per step"]
         md += legs(v, False)
+    with open(out, "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
+def summarize_sweep(out, json_path, command):
+    """Markdown table of a --resolution-sweep JSON line."""
+    d = json.loads(open(json_path).read().strip().splitlines()[-1])
+    md = ["# Conflict resolution vs target-mode length (Sections 5.1-5.3), MI355X, one GPU", "",
+          "Command (GPU box, repository root):", "", f"    {command}", "",
+          "3-mode 2^21 x 2^17 x I tensors, 50M distinct non-zeros (Zipf(1.1) indices on the two "
+          "long modes, uniform on the short one, U(0,1) values), rank "
+          f"{d['rank']} fp32 factors; kernel time of the mode-3 (length I) MTTKRP, output "
+          "accumulated. The register-based path includes its frequent-row stash (all I rows fit "
+          f"for I <= 255). The device reports {d['cus']} compute units; `auto` is the Section 5.3 "
+          "choice (hierarchical when I is below the compute-unit count).", "",
+          "| I | register ms | hierarchical ms | register / hierarchical | auto |",
+          "|---:|---:|---:|---:|---|"]
+    for r in d["rows"]:
+        h = r.get("hierarchical_ms")
+        hs = "-" if h is None else f"{h:.3f}"
+        ratio = "-" if h is None else f"{r['register_ms'] / h:.2f}"
+        md.append(f"| {r['I']} | {r['register_ms']:.3f} | {hs} | {ratio} | {r['auto']} |")
     with open(out, "w") as fh:
         fh.write("\n".join(md) + "\n")
     print("\n".join(md))
@@ -450,6 +478,49 @@ def atomic_calibration(torch, blco, R, steps, rows=1 << 22):
     ms = Timer(torch)(lambda: blco.atomic_probe(out, ids), steps, 2)
     del out, ids
     return {"rows": rows, "rank": R, "ms": ms, "row_ops_per_s": rows / (ms * 1e-3)}
+
+
+def gather_calibration(torch, blco, R, steps, rows=1 << 22):
+    """Random-row gather rate: every row of a rows x R fp32 table read once, in a random
+    order, by 16-lane groups with six rows per group in flight (the MTTKRP gathers)."""
+    dev = torch.device("cuda:0")
+    table = torch.rand((rows, R), dtype=torch.float32, device=dev)
+    g = torch.Generator(device="cpu").manual_seed(2201)
+    ids = torch.randperm(rows, generator=g).to(torch.int32).to(dev)
+    sink = torch.empty(((rows + 5) // 6,), dtype=torch.float32, device=dev)
+    ms = Timer(torch)(lambda: blco.gather_probe(table, ids, sink), steps, 2)
+    del table, ids, sink
+    return {"rows": rows, "rank": R, "ms": ms, "rows_per_s": rows / (ms * 1e-3)}
+
+
+def counter_of(counters, kernel, counter):
+    """Mean per dispatch of one counter of one kernel in a counter summary, or None."""
+    if counters is None:
+        return None
+    k = _kernel_entry(counters[1], kernel)
+    return k.get(counter) if k else None
+
+
+def request_model(counters, kernel, kernel_ms, atomics, gcal):
+    """A kernel's time priced by its memory-side requests: its L2 read misses (TCC_MISS
+    less the memory-side atomics, which L2 also counts as misses) at the rate the gather
+    probe makes them (the probe's TCC_MISS per dispatch over its live time), and its
+    atomic row-updates at the atomic probe's rate.  serial_ms is their sum (the two kinds
+    of request served one after the other), overlap_ms the larger (served side by side);
+    frac = serial_ms / kernel time."""
+    miss = counter_of(counters, kernel, "TCC_MISS_sum")
+    atom = counter_of(counters, kernel, "TCC_EA0_ATOMIC_sum") or 0.0
+    pmiss = counter_of(counters, "k_gather_probe", "TCC_MISS_sum")
+    if miss is None or not pmiss or atomics.get("bound_ms") is None:
+        return None
+    miss = max(miss - atom, 0.0)
+    miss_rate = pmiss / (gcal["ms"] * 1e-3)
+    miss_ms = miss / miss_rate * 1e3
+    serial = miss_ms + atomics["bound_ms"]
+    return {"gather_calibration": gcal, "l2_read_misses_per_launch": miss,
+            "probe_l2_misses_per_s": miss_rate, "miss_ms": miss_ms,
+            "atomic_ms": atomics["bound_ms"], "serial_ms": serial,
+            "overlap_ms": max(miss_ms, atomics["bound_ms"]), "frac": serial / kernel_ms}
 
 
 # --------------------------------------------------------------------------- legs
@@ -560,6 +631,7 @@ def leg_inmemory(args, torch, blco, synth, w, *, check=True, cpu=False, gpu_buil
                "requests_per_row_op": rops["requests_per_row_op"] if rops else None,
                "bound_ms": rops["row_ops"] / calib["row_ops_per_s"] * 1e3 if rops else None}
     atomics["frac"] = atomics["bound_ms"] / avg_ms if rops else None
+    gcal = gather_calibration(torch, blco, R, args.steps)
     res["roofline"] = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
@@ -573,6 +645,7 @@ def leg_inmemory(args, torch, blco, synth, w, *, check=True, cpu=False, gpu_buil
         "all_modes_frac": sum(head["compulsory_bytes"]) / (sum(head["kernel_ms"]) * 1e-3) / 1e9
                           / HBM_PEAK_GBS,
         "atomics": atomics,
+        "request_model": request_model(counters, dom, avg_ms, atomics, gcal),
     }
     log(f"{w.name}: dominant kernel {dom} (modes {dm}): {avg_ms:.3f} ms, {achieved:.0f} GB/s "
         f"compulsory = {achieved / HBM_PEAK_GBS:.3f} of HBM peak; atomics {atomics}")
@@ -961,6 +1034,10 @@ def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-bench":
         # OUT TITLE JSON COMMAND
         summarize_bench(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-sweep":
+        # OUT JSON COMMAND
+        summarize_sweep(sys.argv[2], sys.argv[3], sys.argv[4])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-stats":
         # OUT TITLE STATS_CSV COMMAND

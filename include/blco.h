@@ -312,6 +312,20 @@ int blco_resolution(const blco_tensor* t, int mode, int rank, int* chosen);
 int blco_atomic_probe(float* out, int64_t nrows, int rank, const uint32_t* rows, int64_t n,
                       void* stream);
 
+/*
+ * Measurement kernel, not part of the method: reads rows rows[0..n) of table
+ * (device, nrows x rank fp32) by groups of 16 lanes, six rows per group with all
+ * of a group's loads in flight together (lane l reads ranks l, l + 16, ...), as
+ * the MTTKRP kernels gather factor rows, and stores one partial sum per group in
+ * sink (device, at least ceil(n / 6) floats, overwritten).  Timed over distinct
+ * random rows of a table far larger than L2 it calibrates the random-row gather
+ * rate that, beside the atomic rate, bounds the register-based MTTKRP.  rows:
+ * device, n uint32; ids >= nrows are skipped.
+ * Errors: EINVAL (negative size, rank < 1, null pointer with n > 0).
+ */
+int blco_gather_probe(const float* table, int64_t nrows, int rank, const uint32_t* rows,
+                      int64_t n, float* sink, void* stream);
+
 /* Rows of mode `mode` whose segment sums a register-based MTTKRP at rank
    `rank` on the current device adds into its LDS stash of frequent rows (found
    at build time) instead of the output, in *rows (0: none).  For inspection.

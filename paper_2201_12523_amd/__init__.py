@@ -19,7 +19,7 @@ import torch  # noqa: F401  (must precede loading libblco.so)
 
 __all__ = ["BLCOTensor", "build", "mttkrp", "mttkrp_acc", "mttkrp_v", "mttkrp_stream",
            "mttkrp_stream_all", "sampled_loss", "cp_grad",
-           "cast_bf16", "atomic_probe", "CPLoss", "BLCOError", "lib", "library_path"]
+           "cast_bf16", "atomic_probe", "gather_probe", "CPLoss", "BLCOError", "lib", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libblco.so")
@@ -34,7 +34,7 @@ EXPORTED = ["blco_build", "blco_mttkrp", "blco_mttkrp_acc", "blco_mttkrp_v", "bl
             "blco_mttkrp_stream_all",
             "blco_sampled_loss", "blco_cp_grad", "blco_cp_grad_noalloc", "blco_scale", "blco_cast_bf16", "blco_set_resolution", "blco_resolution",
             "blco_gram", "blco_cp_als", "blco_build_device",
-            "blco_atomic_probe", "blco_frequent_rows", "blco_info", "blco_export", "blco_free",
+            "blco_atomic_probe", "blco_gather_probe", "blco_frequent_rows", "blco_info", "blco_export", "blco_free",
             "blco_last_error"]
 
 
@@ -108,6 +108,7 @@ def lib():
         L.blco_resolution.argtypes = [p, i32, i32, ctypes.POINTER(ctypes.c_int)]
         L.blco_frequent_rows.argtypes = [p, i32, i32, ctypes.POINTER(ctypes.c_int)]
         L.blco_atomic_probe.argtypes = [p, i64, i32, p, i64, p]
+        L.blco_gather_probe.argtypes = [p, i64, i32, p, i64, p, p]
         L.blco_free.argtypes = [p]
         L.blco_free.restype = None
         L.blco_last_error.restype = ctypes.c_char_p
@@ -461,6 +462,23 @@ def atomic_probe(out, rows, stream=None):
     _check(lib().blco_atomic_probe(out.data_ptr(), out.shape[0], out.shape[1], rows.data_ptr(),
                                    rows.numel(), _stream(stream)))
     return out
+
+
+def gather_probe(table, rows, sink, stream=None):
+    """Calibration kernel: reads table[rows[k], :] by 16-lane groups, six rows per group in
+    flight (the MTTKRP kernels' gather pattern), one partial sum per group into sink.
+    table: float32 (I x R) device tensor; rows: int32 device tensor of row ids (uint32
+    bits); sink: float32 device tensor of at least ceil(len(rows) / 6) entries."""
+    if table.dtype != torch.float32 or not table.is_contiguous() or table.dim() != 2:
+        raise ValueError("table must be a contiguous 2-D float32 tensor")
+    if rows.dtype != torch.int32 or not rows.is_contiguous():
+        raise ValueError("rows must be a contiguous int32 tensor")
+    if sink.dtype != torch.float32 or sink.numel() < (rows.numel() + 5) // 6:
+        raise ValueError("sink must be a float32 tensor of at least ceil(len(rows) / 6) entries")
+    _check(lib().blco_gather_probe(table.data_ptr(), table.shape[0], table.shape[1],
+                                   rows.data_ptr(), rows.numel(), sink.data_ptr(),
+                                   _stream(stream)))
+    return sink
 
 
 def gram(A, stream=None):

@@ -1083,6 +1083,37 @@ __global__ __launch_bounds__(256) void k_atomic_probe(float* __restrict__ out, i
   for (int r = rl; r < R; r += 16) unsafeAtomicAdd(dst + r, 1.0f);
 }
 
+// Measurement kernel: groups of 16 lanes read kGatherRows rows of table each (ranks
+// l, l + 16, ... per lane, all loads of a group in flight together), as the MTTKRP
+// kernels gather factor rows; lane 0 of a group stores its partial sum in sink[group].
+constexpr int kGatherRows = 6;
+__global__ __launch_bounds__(256) void k_gather_probe(const float* __restrict__ table,
+                                                      int64_t nrows,
+                                                      const uint32_t* __restrict__ rows,
+                                                      int64_t n, int R, float* __restrict__ sink) {
+  const int64_t g = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
+  const int rl = threadIdx.x & 15;
+  const int64_t k0 = g * kGatherRows;
+  if (k0 >= n) return;
+  uint32_t rr[kGatherRows];
+#pragma unroll
+  for (int j = 0; j < kGatherRows; ++j) {
+    rr[j] = k0 + j < n ? rows[k0 + j] : 0xFFFFFFFFu;
+    if ((int64_t)rr[j] >= nrows) rr[j] = 0xFFFFFFFFu;
+  }
+  float s = 0.f;
+#pragma unroll 4
+  for (int r = rl; r < R; r += 16) {
+    float v[kGatherRows];
+#pragma unroll
+    for (int j = 0; j < kGatherRows; ++j)
+      v[j] = rr[j] != 0xFFFFFFFFu ? table[(size_t)rr[j] * R + r] : 0.f;
+#pragma unroll
+    for (int j = 0; j < kGatherRows; ++j) s += v[j];
+  }
+  if (rl == 0) sink[g] = s;
+}
+
 // x[i] *= (float)(alpha * scale[0]) (the chain-rule factor of an autograd backward).
 __global__ __launch_bounds__(256) void k_scale(float* __restrict__ x, int64_t n,
                                                const double* __restrict__ scale, double alpha) {
@@ -2132,6 +2163,22 @@ extern "C" int blco_atomic_probe(float* out, int64_t nrows, int rank, const uint
   if (blocks > 0x7FFFFFFF) return set_error(BLCO_EINVAL, "n = %lld too large", (long long)n);
   hipLaunchKernelGGL(k_atomic_probe, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                      out, nrows, rows, n, rank);
+  HIPCHK(hipGetLastError());
+  return BLCO_OK;
+}
+
+extern "C" int blco_gather_probe(const float* table, int64_t nrows, int rank,
+                                 const uint32_t* rows, int64_t n, float* sink, void* stream) {
+  clear_error();
+  if (n < 0 || nrows < 0) return set_error(BLCO_EINVAL, "negative size");
+  if (rank < 1) return set_error(BLCO_EINVAL, "rank %d < 1", rank);
+  if (n == 0) return BLCO_OK;
+  if (!table || !rows || !sink) return set_error(BLCO_EINVAL, "table, rows or sink is NULL");
+  const int64_t groups = (n + kGatherRows - 1) / kGatherRows;
+  const int64_t blocks = (groups * 16 + 255) / 256;
+  if (blocks > 0x7FFFFFFF) return set_error(BLCO_EINVAL, "n = %lld too large", (long long)n);
+  hipLaunchKernelGGL(k_gather_probe, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                     table, nrows, rows, n, rank, sink);
   HIPCHK(hipGetLastError());
   return BLCO_OK;
 }

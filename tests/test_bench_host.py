@@ -122,3 +122,22 @@ def test_big_factor_rule(bench):
     assert [bench.big_factors(dims, 64, 4, n) for n in range(4)] == [False, True, True, True]
     assert not any(bench.big_factors(dims, 32, 4, n) for n in range(4))
     assert not any(bench.big_factors(dims, 64, 2, n) for n in range(4))
+
+
+def test_request_model(bench, tmp_path):
+    """L2 read misses priced at the gather probe's rate plus atomics at the atomic probe's."""
+    name = bench.win_kernel_name(32, 4)
+    k = "void " + name + "(blco::KParams)"
+    gp = "k_gather_probe(float const*, long, unsigned int const*, long, int, float*)"
+    f, out = tmp_path / "m.csv", tmp_path / "c.txt"
+    # 3500 misses of which 500 are the kernel's memory-side atomics
+    write_csv(f, [(k, "TCC_MISS_sum", 3500.0), (k, "TCC_MISS_sum", 3500.0),
+                  (k, "TCC_EA0_ATOMIC_sum", 500.0), (gp, "TCC_MISS_sum", 1000.0)])
+    bench.summarize_counters(str(out), "test", str(f), copy_bytes=1 << 20, probe_row_ops=1000)
+    c = bench.read_counters(str(out))
+    # the probe makes 1000 misses in 1 ms: 3000 misses take 3 ms, plus 4 ms of atomics
+    m = bench.request_model(c, name, 10.0, {"bound_ms": 4.0}, {"ms": 1.0})
+    assert m["miss_ms"] == pytest.approx(3.0) and m["overlap_ms"] == pytest.approx(4.0)
+    assert m["serial_ms"] == pytest.approx(7.0) and m["frac"] == pytest.approx(0.7)
+    assert bench.request_model(c, name, 10.0, {"bound_ms": None}, {"ms": 1.0}) is None
+    assert bench.request_model(None, name, 10.0, {"bound_ms": 4.0}, {"ms": 1.0}) is None

@@ -359,6 +359,34 @@ def test_stream_matches_in_memory(budget_nnz, res):
     assert e.value.status == "ENOMEM"
 
 
+def test_calibration_probes():
+    """The two measurement kernels the benchmark times: the atomic probe adds 1 to every
+    entry of each listed row (ids past the table skipped), the gather probe leaves in each
+    group's sink entry lane 0's sum over its six rows (ranks 0 and 16 at R = 32)."""
+    R, I = 32, 1000
+    rng = np.random.default_rng(5)
+    ids = rng.integers(0, I + 50, size=4001).astype(np.int64)   # some ids past the table
+    out = torch.zeros((I, R), dtype=torch.float32, device=DEV)
+    rows = torch.from_numpy(ids.astype(np.int32)).to(DEV)
+    blco.atomic_probe(out, rows)
+    want = np.zeros((I, R))
+    for i in ids[ids < I]:
+        want[i] += 1.0
+    assert np.array_equal(out.cpu().numpy(), want)
+    table = (torch.arange(I, dtype=torch.float32, device=DEV)[:, None] * 100.0 +
+             torch.arange(R, dtype=torch.float32, device=DEV)[None, :])
+    sink = torch.full(((len(ids) + 5) // 6,), -1.0, dtype=torch.float32, device=DEV)
+    blco.gather_probe(table, rows, sink)
+    tab = table.cpu().numpy().astype(np.float64)
+    exp = np.zeros(len(sink))
+    for k, i in enumerate(ids):
+        if i < I:
+            exp[k // 6] += tab[i, 0] + tab[i, 16]
+    assert np.allclose(sink.cpu().numpy(), exp, rtol=1e-6)
+    with pytest.raises(ValueError):
+        blco.gather_probe(table, rows, sink[:10])
+
+
 def test_argument_errors():
     rng = np.random.default_rng(1)
     dims = (10, 10, 10)
