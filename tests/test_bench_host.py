@@ -141,3 +141,40 @@ def test_request_model(bench, tmp_path):
     assert m["serial_ms"] == pytest.approx(7.0) and m["frac"] == pytest.approx(0.7)
     assert bench.request_model(c, name, 10.0, {"bound_ms": None}, {"ms": 1.0}) is None
     assert bench.request_model(None, name, 10.0, {"bound_ms": 4.0}, {"ms": 1.0}) is None
+
+
+def test_summaries_of_bench_and_sweep_lines(bench, tmp_path):
+    """The markdown summaries carry the line's figures: value, roofline with traffic,
+    atomics and request pricing, per-configuration times, errors and secondary legs."""
+    import json
+
+    roof = {"bound": "hbm", "kernel": "k", "modes": [0], "avg_kernel_ms": 2.0,
+            "algorithmic_bytes_per_launch": 4e9, "achieved": 2000.0, "frac": 0.25,
+            "traffic": 8e9, "traffic_over_algorithmic": 2.0,
+            "atomics": {"row_ops_per_launch": 1e6, "frac": 0.5},
+            "request_model": {"miss_ms": 0.5, "atomic_ms": 1.0, "serial_ms": 1.5, "frac": 0.75}}
+    line = {"metric": "m", "value": 12.5, "unit": "Gnnz/s", "ms_per_step": 8.0,
+            "config": {"workload": "w: shape"}, "roofline": roof,
+            "per_config": {"R32_fp32": {"ms_per_step": 8.0, "gnnz_s": 12.5, "kernel_ms": [2.0],
+                                        "resolution": ["register"]}},
+            "errors": {"R32_fp32": {"max": 1.5e-7}},
+            "secondary": {"oom": {"value": 3.0, "unit": "Gnnz/s", "ms_per_step": 100.0,
+                                  "roofline": {"bound": "pcie", "achieved": 50.0}}}}
+    j = tmp_path / "b.json"
+    j.write_text("progress text\n" + json.dumps(line) + "\n")
+    out = tmp_path / "b.md"
+    bench.summarize_bench(str(out), "test", str(j), "python3 bench.py")
+    md = out.read_text()
+    for want in ("12.500 Gnnz/s", "0.250 of 8 TB/s", "counter traffic 8.00 GB", "(2.0x)",
+                 "atomic row-updates 1.0M = 0.50", "= 1.50 ms = 0.75", "R32_fp32: 8.000 ms",
+                 "R32_fp32 1.50e-07", "## secondary: oom", "host link: 50.0 GB/s"):
+        assert want in md, want
+    sweep = {"rank": 32, "cus": 256, "rows": [
+        {"I": 4, "register_ms": 1.2, "hierarchical_ms": 1.0, "auto": "hierarchical"},
+        {"I": 512, "register_ms": 0.9, "hierarchical_ms": None, "auto": "register"}]}
+    j2, out2 = tmp_path / "s.json", tmp_path / "s.md"
+    j2.write_text(json.dumps(sweep) + "\n")
+    bench.summarize_sweep(str(out2), str(j2), "python3 bench.py --resolution-sweep")
+    md2 = out2.read_text()
+    assert "| 4 | 1.200 | 1.000 | 1.20 | hierarchical |" in md2
+    assert "| 512 | 0.900 | - | - | register |" in md2
