@@ -405,6 +405,23 @@ def summarize_sweep(out, json_path, command):
     print("\n".join(md))
 
 
+def summarize_skew(out, json_path, command):
+    """Markdown table of an --atomic-skew JSON line."""
+    d = json.loads(open(json_path).read().strip().splitlines()[-1])
+    md = ["# fp32 atomic row-updates vs row skew (MI355X, one GPU)", "",
+          "Command (GPU box, repository root):", "", f"    {command}", "",
+          f"The library's atomic probe (`blco_atomic_probe`: one row-update of R = {d['rank']} "
+          f"floats by 16 lanes, as the MTTKRP flushes) over {d['updates']} updates of a "
+          f"{d['table_rows']}-row fp32 output.", "",
+          "| rows | ms | row-updates/s | most updates on one row |", "|---|---:|---:|---:|"]
+    for r in d["results"]:
+        md.append(f"| {r['rows']} | {r['ms']:.3f} | {r['row_updates_per_s'] / 1e9:.2f}G | "
+                  f"{r['most_updates_on_one_row']} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 # --------------------------------------------------------------------------- helpers
 
 def win_kernel_name(R, N, ft="float", big=False, stash=True):
@@ -906,6 +923,35 @@ def leg_cpals(args, torch, blco, synth, w):
     return res
 
 
+def atomic_skew(args, torch, blco):
+    """The atomic probe (one 16-lane row-update per entry, R = 32) over 2^22 updates of a
+    2^24-row output: rows uniform, or Zipf(1.2) ranks without the K most frequent (the rows
+    a stash would hold), ranks spread over the rows by an odd multiplier mod 2^24."""
+    rows, n, R = 1 << 24, 1 << 22, 32
+    dev = torch.device("cuda:0")
+    out = torch.zeros((rows, R), dtype=torch.float32, device=dev)
+    cdf = np.cumsum(np.arange(1, rows + 1, dtype=np.float64) ** -1.2)
+    rng = np.random.default_rng(1225)
+    timer = Timer(torch)
+    res = []
+    for K in (None, 0, 256, 4096, 65536):
+        if K is None:
+            ids = rng.integers(0, rows, n)
+        else:
+            lo = cdf[K - 1] if K > 0 else 0.0
+            ranks = np.searchsorted(cdf, lo + rng.random(n) * (cdf[-1] - lo), side="right")
+            ids = (np.minimum(ranks, rows - 1).astype(np.uint64) * np.uint64(2654435761)) & \
+                np.uint64(rows - 1)
+        t = torch.from_numpy(ids.astype(np.uint32).view(np.int32)).to(dev)
+        ms = timer(lambda: blco.atomic_probe(out, t), args.steps, 2)
+        top = int(np.bincount(ids.astype(np.int64), minlength=rows).max())
+        res.append({"rows": "uniform" if K is None else f"zipf1.2 without the top {K}",
+                    "ms": ms, "row_updates_per_s": n / (ms * 1e-3), "most_updates_on_one_row": top})
+        log(f"atomic skew {res[-1]}")
+    return {"probe": "fp32 atomic row-updates vs row skew", "updates": n, "table_rows": rows,
+            "rank": R, "results": res}
+
+
 def resolution_sweep(args, torch, blco, synth):
     """Both conflict-resolution mechanisms (Sections 5.1-5.2) on the short mode of
     3-mode 2^21 x 2^17 x I tensors (Zipf(1.1) long modes, uniform short mode),
@@ -1035,6 +1081,10 @@ def main():
         # OUT TITLE JSON COMMAND
         summarize_bench(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
         return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-skew":
+        # OUT JSON COMMAND
+        summarize_skew(sys.argv[2], sys.argv[3], sys.argv[4])
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-sweep":
         # OUT JSON COMMAND
         summarize_sweep(sys.argv[2], sys.argv[3], sys.argv[4])
@@ -1062,6 +1112,8 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the oracle row checks")
     ap.add_argument("--oom-start-limit-s", type=float, default=300.0,
                     help="default run: skip the 1.5B-non-zero leg when it would start later")
+    ap.add_argument("--atomic-skew", action="store_true",
+                    help="atomic probe rate over uniform and Zipf-distributed rows")
     ap.add_argument("--resolution-sweep", action="store_true",
                     help="time both conflict-resolution mechanisms over short-mode lengths")
     ap.add_argument("--rank", type=int, default=32,
@@ -1092,6 +1144,9 @@ def main():
         del src, dst
     if args.resolution_sweep:
         print(json.dumps(resolution_sweep(args, torch, blco, synth)), flush=True)
+        return
+    if args.atomic_skew:
+        print(json.dumps(atomic_skew(args, torch, blco)), flush=True)
         return
     W = synth.WORKLOADS
     check, cpu = not args.no_check, not args.no_cpu_baseline

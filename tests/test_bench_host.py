@@ -178,3 +178,9 @@ def test_summaries_of_bench_and_sweep_lines(bench, tmp_path):
     md2 = out2.read_text()
     assert "| 4 | 1.200 | 1.000 | 1.20 | hierarchical |" in md2
     assert "| 512 | 0.900 | - | - | register |" in md2
+    skew = {"updates": 4, "table_rows": 16, "rank": 32, "results": [
+        {"rows": "uniform", "ms": 0.5, "row_updates_per_s": 8e9, "most_updates_on_one_row": 1}]}
+    j3, out3 = tmp_path / "k.json", tmp_path / "k.md"
+    j3.write_text(json.dumps(skew) + "\n")
+    bench.summarize_skew(str(out3), str(j3), "python3 bench.py --atomic-skew")
+    assert "| uniform | 0.500 | 8.00G | 1 |" in out3.read_text()
