@@ -167,6 +167,47 @@ def test_window_boundaries(nnz, N):
              resolutions=("register", "frequent"))
 
 
+@pytest.mark.parametrize("dtype,R", [("fp32", 64), ("bf16", 64), ("bf16", 34)])
+def test_register_path_factor_past_4gib(dtype, R):
+    """Register-based MTTKRP of the two short modes when the long mode's factor is just
+    past 4 GiB, so the kernel gathers through 64-bit addresses instead of 32-bit buffer
+    offsets, with and without the frequent-row stash (packed bf16 ranks at R = 34)."""
+    fsz = 4 if dtype == "fp32" else 2
+    rows0 = max(1 << 24, (1 << 32) // (R * fsz) + 1)
+    assert rows0 * R * fsz > 0xFFFFFFFF
+    rng = np.random.default_rng(R + fsz)
+    dims = (rows0, 100, 60)
+    nnz = 300_000
+    coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
+    coords[0][:1000] = rows0 - 1
+    vals = rng.random(nnz).astype(np.float32)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(R)
+    F0 = torch.randn((rows0, R), device=DEV, generator=g)
+    if dtype == "bf16":
+        F0 = blco.cast_bf16(F0)
+    torch.cuda.empty_cache()
+    A1 = rng.standard_normal((dims[1], R)).astype(np.float32)
+    A2 = rng.standard_normal((dims[2], R)).astype(np.float32)
+    F = [F0] + _dev_factors([A1, A2], torch.bfloat16 if dtype == "bf16" else torch.float32)
+    used, inv = np.unique(coords[0], return_inverse=True)
+    A0 = F0[torch.from_numpy(used.astype(np.int64)).to(DEV)].float().cpu().numpy()
+    Aref = [A0] + ([A1, A2] if dtype == "fp32" else [_bf16_round(A1), _bf16_round(A2)])
+    small = [inv.astype(np.uint32), coords[1], coords[2]]
+    for hot in (0, -1):   # 0: default frequent rows (stash); -1: none
+        t = blco.build(coords, vals, dims, hot_min_count=hot)
+        t.set_resolution("register")
+        for n in (1, 2):
+            out = blco.mttkrp(t, n, F)
+            M, S = oracle.mttkrp(small, vals, Aref, n)
+            say(f"{dtype} R={R} rows0={rows0} hot={hot} mode {n}: stash rows {t.stash_rows(n, R)}")
+            check_entries(out.cpu().numpy(), M, S, label=f"{dtype} R={R} hot={hot} mode {n}")
+            del out
+        t.free()
+    del F0, F
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("pattern", ["one_row", "distinct", "lane_mod_3", "tail_65", "tail_1"])
 def test_conflict_patterns(pattern):
     rng = np.random.default_rng(7)
