@@ -442,7 +442,7 @@ def short_kernel_name(R, N, ft="float", big=False):
     """Template name of the hierarchical MTTKRP kernel for a single rank slice of width R
     (vector gathers of packed bf16 ranks: bf16, two or more ranks per lane, even R)."""
     rpl = 1 if R <= 16 else 2 if R <= 32 else 4
-    vec = ft != "float" and rpl > 1 and R % 2 == 0 and not big
+    vec = ft != "float" and rpl > 1 and R % 2 == 0
     b = lambda v: "true" if v else "false"
     return f"k_mttkrp_short<{rpl}, {ft}, {N}, {b(big)}, {b(vec)}>"
 

@@ -242,6 +242,27 @@ __device__ __forceinline__ void ld_bf16_run(__amdgpu_buffer_rsrc_t r, uint32_t o
   for (int k = 0; k < RPL; ++k) t[k] = ld_buf<uint16_t>(r, off + 2u * (uint32_t)k);
 }
 
+// The same run through a 64-bit address (a factor of 4 GiB or more), which has no
+// bounds check: only elements with act[k] set (ranks below R) are read, so a run that
+// ends past the last row stays inside the factor.  VEC reads RPL / 2 four-byte words
+// (runs start 4-byte aligned and R is even, so a word is read whole or not at all).
+template <int RPL, bool VEC>
+__device__ __forceinline__ void ld_bf16_run_ptr(const uint16_t* src, const bool (&act)[RPL],
+                                                float (&t)[RPL]) {
+  if constexpr (VEC && RPL % 2 == 0) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(src);
+#pragma unroll
+    for (int q = 0; q < RPL / 2; ++q) {
+      const uint32_t v = act[2 * q] ? w[q] : 0u;
+      t[2 * q] = __uint_as_float(v << 16);
+      t[2 * q + 1] = __uint_as_float(v & 0xFFFF0000u);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) t[k] = act[k] ? ld_factor<uint16_t>(src, (size_t)k) : 0.f;
+  }
+}
+
 // Adds a lane group's segment sums to one output row with contiguous-rank atomics
 // when each lane holds RPL consecutive ranks (lane l: ranks RPL*l .. RPL*l + RPL - 1 of
 // the slice): the j-th atomic of lane l adds rank l + j*LPN, fetched from the lane
@@ -568,7 +589,13 @@ __global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
 #pragma unroll
           for (int j = 0; j + 1 < N; ++j) {
             const uint32_t f = kRowB ? e[j] : er[j];
-            if constexpr (BIG) {
+            if constexpr (BIG && PACKED) {
+              const FT* rowp = static_cast<const FT*>(ap[j]) + (size_t)f * R;
+              float t3[RPL];
+              ld_bf16_run_ptr<RPL, VEC>(rowp + loff[0] / sizeof(FT), ract, t3);
+#pragma unroll
+              for (int k = 0; k < RPL; ++k) pr[u][k] *= t3[k];
+            } else if constexpr (BIG) {
               const FT* rowp = static_cast<const FT*>(ap[j]) + (size_t)f * R;
 #pragma unroll
               for (int k = 0; k < RPL; ++k)
@@ -832,7 +859,13 @@ __global__ __launch_bounds__(kShortB, 8) void k_mttkrp_short(KParams p, int64_t 
           for (int q = 0; q < RPL; ++q) pr[u][q] = xv;
 #pragma unroll
           for (int jj = 0; jj + 1 < N; ++jj) {
-            if constexpr (BIG) {
+            if constexpr (BIG && PACKED) {
+              const FT* rowp = static_cast<const FT*>(ap[jj]) + (size_t)e[jj] * p.R;
+              float t3[RPL];
+              ld_bf16_run_ptr<RPL, VEC>(rowp + loff[0] / sizeof(FT), ract, t3);
+#pragma unroll
+              for (int q = 0; q < RPL; ++q) pr[u][q] *= t3[q];
+            } else if constexpr (BIG) {
               const FT* rowp = static_cast<const FT*>(ap[jj]) + (size_t)e[jj] * p.R;
 #pragma unroll
               for (int q = 0; q < RPL; ++q)
@@ -1232,7 +1265,7 @@ static ShortFn pick_short_v(int N) {
 // VEC where the bf16 ranks are packed (two or more per lane) and R is even
 template <int RPL, typename FT, bool BIG>
 static ShortFn pick_short(int N, int R) {
-  if constexpr (sizeof(FT) == 2 && RPL > 1 && !BIG) {
+  if constexpr (sizeof(FT) == 2 && RPL > 1) {
     if (R % 2 == 0) return pick_short_v<RPL, FT, BIG, true>(N);
   }
   return pick_short_v<RPL, FT, BIG, false>(N);

@@ -117,32 +117,44 @@ def test_every_nonzero_on_one_row(dtype):
     check_entries(out.cpu().numpy(), M, S, label=f"one row {dtype}")
 
 
-def test_factor_past_4gib():
-    # mode 0 has 2^24 rows at R = 64: its fp32 factor is 4 GiB, so the
-    # hierarchical kernel gathers it with 64-bit addresses
+@pytest.mark.parametrize("dtype,R", [("fp32", 64), ("bf16", 64), ("bf16", 34)])
+def test_factor_past_4gib(dtype, R):
+    # mode 0's factor is just past 4 GiB (2^24 rows at R = 64 in fp32; more rows in
+    # bf16), so the hierarchical kernel gathers it with 64-bit addresses; in bf16 at
+    # R = 34 the last lane's packed run ends past the row, and past the factor on its
+    # last row, which is referenced
+    fsz = 4 if dtype == "fp32" else 2
+    rows0 = max(1 << 24, (1 << 32) // (R * fsz) + 1)
+    assert rows0 * R * fsz > 0xFFFFFFFF
     rng = np.random.default_rng(9)
-    dims = (1 << 24, 100, 60)
+    dims = (rows0, 100, 60)
     nnz = 300_000
     coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
-    coords[0][:1000] = (1 << 24) - 1
+    coords[0][:1000] = rows0 - 1
     vals = rng.random(nnz).astype(np.float32)
     t = blco.build(coords, vals, dims)
-    R = 64
     g = torch.Generator(device=DEV)
     g.manual_seed(9)
     F0 = torch.randn((dims[0], R), device=DEV, generator=g)
     A1 = rng.standard_normal((dims[1], R)).astype(np.float32)
     A2 = rng.standard_normal((dims[2], R)).astype(np.float32)
     F = [F0, dev(A1), dev(A2)]
+    A12 = [A1, A2]
+    if dtype == "bf16":
+        F = [blco.cast_bf16(f) for f in F]
+        del F0
+        F0 = F[0]
+        torch.cuda.empty_cache()
+        A12 = [oracle.bf16_round(a) for a in A12]
     # the oracle sees only the referenced rows of the big factor
     used, inv = np.unique(coords[0], return_inverse=True)
-    A0 = F0[torch.from_numpy(used.astype(np.int64)).to(DEV)].cpu().numpy()
+    A0 = F0[torch.from_numpy(used.astype(np.int64)).to(DEV)].float().cpu().numpy()
     small = [inv.astype(np.uint32), coords[1], coords[2]]
     for n in (1, 2):
         assert t.resolution(n, R) == "hierarchical"
         out = blco.mttkrp(t, n, F)
-        M, S = oracle.mttkrp(small, vals, [A0, A1, A2], n)
-        check_entries(out.cpu().numpy(), M, S, label=f"4 GiB factor mode {n}")
+        M, S = oracle.mttkrp(small, vals, [A0] + A12, n)
+        check_entries(out.cpu().numpy(), M, S, label=f"4 GiB factor {dtype} R={R} mode {n}")
     del F0, F
     torch.cuda.empty_cache()
 
