@@ -431,9 +431,10 @@ def win_kernel_name(R, N, ft="float", big=False, stash=True):
     b = lambda v: "true" if v else "false"
     # then: the fused CP-gradient walk (never for the plain MTTKRP), vector gathers of
     # packed bf16 ranks (bf16 factors, two or more ranks per lane, even R), and the
-    # non-zeros per thread (two without a stash at R <= 64 and at most 5 modes)
+    # non-zeros per thread (without a stash at R <= 64 and at most 5 modes: two, four at
+    # R > 32)
     vec = ft != "float" and rpl > 1 and R % 2 == 0
-    wpt = 2 if (not stash and lpn == 16 and N <= 5) else 1
+    wpt = (4 if rpl == 4 else 2) if (not stash and lpn == 16 and N <= 5) else 1
     return (f"k_mttkrp_win<{lpn}, {rpl}, {ft}, {N}, {b(big)}, {b(stash)}, false, {b(vec)}, "
             f"{wpt}>")
 

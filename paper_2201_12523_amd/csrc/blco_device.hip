@@ -338,18 +338,20 @@ __device__ __forceinline__ int hot_lookup(const uint32_t* keys, const uint32_t* 
 //
 // WPT: non-zeros per thread, so a window holds kWin * WPT non-zeros.  Two (for modes
 // without a stash) merge more terms per flush: on the 2^20-row and 1024-row modes of
-// the 4-mode 200M-non-zero tensor, 16% and 32% fewer row flushes than at one.
+// the 4-mode 200M-non-zero tensor, 16% and 32% fewer row flushes than at one.  Four
+// (at R > 32) merge more again but need 145 KiB of LDS, one workgroup per CU: faster
+// at R = 64, where the walk has four ranks per lane to cover the gathers, slower at 32.
 template <int LPN, int RPL, typename FT, int N, bool BIG, bool STASH, bool RES = false,
           bool VEC = false, int WPT = 1>
-__global__ __launch_bounds__(kWin, BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
+__global__ __launch_bounds__(kWin, WPT >= 4 ? 4 : BLCO_WIN_OCC) void k_mttkrp_win(KParams p) {
   constexpr int W = kWin * WPT;                 // non-zeros per window
   constexpr int G = kWin / LPN;                 // groups of LPN lanes
   constexpr int PPG = W / G;                    // grouped positions per group (= LPN * WPT)
   static_assert(PPG <= 64, "a group's segment ends must fit one 64-bit word");
   static_assert(WPT == 1 || (!STASH && !RES), "multi-non-zero windows: plain MTTKRP, no stash");
   // hash buckets: 4096 per 1024 non-zeros, 6144 per 2048 (two workgroups per CU keep
-  // fitting in LDS)
-  constexpr int NB = WPT == 1 ? kBuckets : kBuckets * 3 / 2;
+  // fitting in LDS), 12288 per 4096
+  constexpr int NB = WPT == 1 ? kBuckets : WPT == 2 ? kBuckets * 3 / 2 : kBuckets * 3;
   // positions whose gathers are issued together: BLCO_WIN_U / RPL, except for
   // 3-mode tensors at one or four ranks per lane, where 4 and 1 positions keep
   // the registers from spilling and measured 8% and 3% faster; the fused
@@ -1173,40 +1175,44 @@ static KernelFn pick_win_s(int N) {
   }
 }
 
-// windows of 2048 non-zeros (two per thread; no stash), up to 5 modes
+// windows of 2048 or 4096 non-zeros (two or four per thread; no stash), up to 5 modes
 constexpr int kWideMaxN = 5;
-template <int LPN, int RPL, typename FT, bool BIG, bool VEC>
+template <int LPN, int RPL, typename FT, bool BIG, bool VEC, int WPT>
 static KernelFn pick_win_wide(int N) {
   switch (N) {
-    case 1: return k_mttkrp_win<LPN, RPL, FT, 1, BIG, false, false, VEC, 2>;
-    case 2: return k_mttkrp_win<LPN, RPL, FT, 2, BIG, false, false, VEC, 2>;
-    case 3: return k_mttkrp_win<LPN, RPL, FT, 3, BIG, false, false, VEC, 2>;
-    case 4: return k_mttkrp_win<LPN, RPL, FT, 4, BIG, false, false, VEC, 2>;
-    default: return k_mttkrp_win<LPN, RPL, FT, 5, BIG, false, false, VEC, 2>;
+    case 1: return k_mttkrp_win<LPN, RPL, FT, 1, BIG, false, false, VEC, WPT>;
+    case 2: return k_mttkrp_win<LPN, RPL, FT, 2, BIG, false, false, VEC, WPT>;
+    case 3: return k_mttkrp_win<LPN, RPL, FT, 3, BIG, false, false, VEC, WPT>;
+    case 4: return k_mttkrp_win<LPN, RPL, FT, 4, BIG, false, false, VEC, WPT>;
+    default: return k_mttkrp_win<LPN, RPL, FT, 5, BIG, false, false, VEC, WPT>;
   }
 }
 
-// Non-zeros per thread of the window kernel: two for a plain MTTKRP without a stash
-// over 16-lane groups (R <= 64) and at most kWideMaxN modes, else one.
+// Non-zeros per thread of the window kernel: for a plain MTTKRP without a stash over
+// 16-lane groups and at most kWideMaxN modes, two at R <= 32 and four at 32 < R <= 64
+// (four ranks per lane); else one.
 static int win_wpt(int N, int R, bool stash, bool resid) {
-  return (!stash && !resid && R <= 64 && N <= kWideMaxN) ? 2 : 1;
+  if (stash || resid || R > 64 || N > kWideMaxN) return 1;
+  return R > 32 ? 4 : 2;
 }
 
 // VEC (vector gathers of packed bf16 ranks) only where the ranks are packed: bf16
 // factors, two or more ranks per lane, and an even R
 template <int LPN, int RPL, typename FT, bool BIG>
 static KernelFn pick_win(int N, int R, bool stash) {
-  const bool wide = win_wpt(N, R, stash, false) == 2;
+  // the wide window of this rank layout (win_wpt's rule: four ranks per lane take four)
+  constexpr int WW = RPL == 4 ? 4 : 2;
+  const bool wide = win_wpt(N, R, stash, false) > 1;
   if constexpr (sizeof(FT) == 2 && RPL > 1) {
     if (R % 2 == 0) {
       if constexpr (LPN == 16)
-        if (wide) return pick_win_wide<LPN, RPL, FT, BIG, true>(N);
+        if (wide) return pick_win_wide<LPN, RPL, FT, BIG, true, WW>(N);
       return stash ? pick_win_s<LPN, RPL, FT, BIG, true, true>(N)
                    : pick_win_s<LPN, RPL, FT, BIG, false, true>(N);
     }
   }
   if constexpr (LPN == 16)
-    if (wide) return pick_win_wide<LPN, RPL, FT, BIG, false>(N);
+    if (wide) return pick_win_wide<LPN, RPL, FT, BIG, false, WW>(N);
   return stash ? pick_win_s<LPN, RPL, FT, BIG, true, false>(N)
                : pick_win_s<LPN, RPL, FT, BIG, false, false>(N);
 }

@@ -49,6 +49,8 @@ def test_kernel_names(bench):
         "k_mttkrp_win<16, 4, unsigned short, 4, false, true, false, false, 1>"
     assert bench.win_kernel_name(32, 6, stash=False) == \
         "k_mttkrp_win<16, 2, float, 6, false, false, false, false, 1>"
+    assert bench.win_kernel_name(64, 4, stash=False) == \
+        "k_mttkrp_win<16, 4, float, 4, false, false, false, false, 4>"
     assert bench.win_kernel_name(100, 4, stash=False) == \
         "k_mttkrp_win<64, 2, float, 4, false, false, false, false, 1>"
     assert bench.short_kernel_name(32, 4) == "k_mttkrp_short<2, float, 4, false, false>"

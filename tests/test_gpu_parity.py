@@ -154,16 +154,19 @@ def test_mode_counts(N):
 
 
 @pytest.mark.parametrize("N", [3, 4])
-@pytest.mark.parametrize("nnz", [1023, 1025, 2047, 2048, 2049, 4095, 6145])
-def test_window_boundaries(nnz, N):
-    """Non-zero counts around the 1024- and 2048-non-zero windows (modes without a
-    stash take two non-zeros per thread): a 7-row mode whose segments run across many
-    lane groups, a 5000-row mode with short ones, and the stash path beside them."""
-    rng = np.random.default_rng(nnz * 10 + N)
+@pytest.mark.parametrize("nnz,R", [(1023, 32), (1025, 32), (2047, 32), (2048, 32), (2049, 32),
+                                   (4095, 32), (6145, 32), (2049, 64), (4095, 64), (4096, 64),
+                                   (4097, 64), (8193, 64)])
+def test_window_boundaries(nnz, R, N):
+    """Non-zero counts around the 1024-, 2048- and 4096-non-zero windows (modes without a
+    stash take two non-zeros per thread at R <= 32, four at R = 64): a 7-row mode whose
+    segments run across many lane groups, a 5000-row mode with short ones, and the
+    stash path beside them."""
+    rng = np.random.default_rng(nnz * 10 + N + R)
     dims = (7, 300, 5000, 3)[:N]
     coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
     vals = rng.standard_normal(nnz).astype(np.float32)
-    run_case(coords, vals, dims, 32, seed=nnz, label=f"win{nnz}N{N}", dtypes=("fp32", "bf16"),
+    run_case(coords, vals, dims, R, seed=nnz, label=f"win{nnz}R{R}N{N}", dtypes=("fp32", "bf16"),
              resolutions=("register", "frequent"))
 
 
