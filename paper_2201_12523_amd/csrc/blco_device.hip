@@ -5,9 +5,9 @@
 // computing split of Section 5.1 (Figure 7), re-designed for wave64 and the
 // memory-side atomics of MI355X:
 //   k_mttkrp_win (register-based resolution, Section 5.2): one 1024-thread
-//     workgroup per window of 1024 consecutive non-zeros (2048 on modes without
-//     frequent rows).  Processing: each
-//     thread loads one or two (key, value) pairs (coalesced), decodes the coordinates
+//     workgroup per window of 1024 consecutive non-zeros (2048 or 4096 on modes
+//     without frequent rows).  Processing: each thread loads one, two or four
+//     (key, value) pairs (coalesced), decodes the coordinates
 //     by shift and mask (Figure 6b), and the window is grouped by target row
 //     with a counting sort on a hash of the target (LDS histogram, workgroup
 //     scan, scatter), so each target forms one segment; every grouped position
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, int64_
   }
 }
 
-constexpr int kWin = 1024;     // non-zeros per window (one per thread of the workgroup)
+constexpr int kWin = 1024;     // threads of the window kernel (non-zeros per window / WPT)
 constexpr int kWinRounds = 4;  // dispatch rounds of the persistent window kernel
 constexpr int kWinBits = 10;
 #ifndef BLCO_WIN_U
@@ -114,7 +114,7 @@ constexpr int kWinBits = 10;
 #endif
 
 constexpr int kBucketBits = 12;
-constexpr int kBuckets = 1 << kBucketBits;   // hash buckets per window
+constexpr int kBuckets = 1 << kBucketBits;   // hash buckets per 1024-non-zero window
 
 // In-place exclusive prefix sum of NB counters in LDS by a workgroup of NT
 // threads (NB a multiple of NT): per-thread serial sums, a wave scan by
