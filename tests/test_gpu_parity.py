@@ -143,14 +143,16 @@ def test_ranks(R):
     run_case(coords, vals, dims, R, seed=R, label=f"rank{R}", dtypes=("fp32", "bf16"))
 
 
+@pytest.mark.parametrize("R", [8, 48])
 @pytest.mark.parametrize("N", [1, 2, 4, 5, 6, 7, 8])
-def test_mode_counts(N):
-    rng = np.random.default_rng(N + 50)
+def test_mode_counts(N, R):
+    # R = 48 at N <= 5: the 4096-non-zero window (the largest LDS use at N = 5)
+    rng = np.random.default_rng(N + 50 + R)
     dims = tuple([13, 1, 7, 30, 5, 9, 3, 17][:N])
-    nnz = 777
+    nnz = 777 if R == 8 else 5000
     coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
     vals = rng.standard_normal(nnz).astype(np.float32)
-    run_case(coords, vals, dims, 8, seed=N, label=f"N{N}")
+    run_case(coords, vals, dims, R, seed=N, label=f"N{N}R{R}")
 
 
 @pytest.mark.parametrize("N", [3, 4])
@@ -376,13 +378,13 @@ def test_cast_bf16_matches_torch():
 
 @pytest.mark.parametrize("res", ["register", "hierarchical"])
 @pytest.mark.parametrize("budget_nnz", [64, 1000, 5000])
-def test_stream_matches_in_memory(budget_nnz, res):
-    rng = np.random.default_rng(budget_nnz)
+@pytest.mark.parametrize("R", [16, 64])
+def test_stream_matches_in_memory(budget_nnz, res, R):
+    rng = np.random.default_rng(budget_nnz + R)
     dims = (300, 200, 100)
     nnz = 20_000
     coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
     vals = rng.random(nnz).astype(np.float32)
-    R = 16
     A = [rng.standard_normal((d, R)).astype(np.float32) for d in dims]
     F = _dev_factors(A)
     tp = blco.build(coords, vals, dims, placement="pinned")
