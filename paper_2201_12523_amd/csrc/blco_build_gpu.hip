@@ -5,14 +5,16 @@
 //   1. ALTO linearization of every coordinate (Section 4.1): bit j of mode n
 //      goes to position pos[n][j] of a 64- or 128-bit index (per-byte deposit
 //      tables); out-of-range coordinates are flagged;
-//   2. a stable radix sort of (index, non-zero number) pairs (blco_sort.hip):
-//      one sort over the low 64 bits, then, for indices over 64 bits, one over
-//      the high bits of the indices gathered in that order (least significant
-//      digits first);
+//   2. a stable radix sort along the encoding line (blco_sort.hip), least
+//      significant digits first: one sort over the low 64 bits, then, for
+//      indices over 64 bits, one over the high bits.  Indices of at most 96 bits
+//      move the values and the high bits through the first sort and the values
+//      and the low bits through the second; wider ones sort (index, non-zero
+//      number) pairs and gather the high bits, then the low bits, in each order;
 //   3. re-encoding in sorted order (Figure 6b) from the sorted index: every
 //      index bit below K moves to its mode's field (a byte table), the block
-//      key is the index above bit K; the values rode along in the sort (index
-//      of at most 64 bits) or follow the permutation (wider index);
+//      key is the index above bit K; the values rode along in the sort, or, for
+//      indices over 96 bits, follow the permutation;
 //   4. runs of equal block key (flags and a stream compaction), copied to the host, where
 //      the block list, per-run high bits and tile table are finished by the
 //      same code as the host builder;
@@ -51,20 +53,23 @@ struct LinParams {
   int T;
 };
 
-// ALTO index of every non-zero (lo: bits 0..63, hi: bits 64..127 or NULL) and,
-// when idx is given, its number; *bad = smallest non-zero number with a
-// coordinate out of range.  dep[((m * 4 + k) * 256 + v) * 2 + {0, 1}]: the
-// (lo, hi) index bits of byte k of a mode-m coordinate holding v.  With hi ==
-// NULL the lo halves of the table are staged in LDS (N * 8 KiB of dynamic LDS),
-// once per workgroup of a grid that strides over the non-zeros.
+// ALTO index of every non-zero (lo: bits 0..63; hi: bits 64..127, or hi32: bits
+// 64..95 of an index of at most 96 bits; or neither) and, when idx is given, its
+// number; *bad = smallest non-zero number with a coordinate out of range.
+// dep[((m * 4 + k) * 256 + v) * 2 + {0, 1}]: the (lo, hi) index bits of byte k of a
+// mode-m coordinate holding v.  Without a high part the lo halves of the table are
+// staged in LDS (N * 8 KiB of dynamic LDS), once per workgroup of a grid that
+// strides over the non-zeros.
 __global__ __launch_bounds__(256) void k_linearize(LinParams p, int64_t n,
                                                    const uint64_t* __restrict__ dep,
                                                    uint64_t* __restrict__ lo,
                                                    uint64_t* __restrict__ hi,
+                                                   uint32_t* __restrict__ hi32,
                                                    uint32_t* __restrict__ idx,
                                                    unsigned long long* __restrict__ bad) {
-  extern __shared__ uint64_t s_dep[];   // [(m * 4 + k) * 256 + v], lo halves (hi == NULL)
-  if (!hi) {
+  extern __shared__ uint64_t s_dep[];   // [(m * 4 + k) * 256 + v], lo halves (no high part)
+  const bool wide = hi || hi32;
+  if (!wide) {
     for (int j = threadIdx.x; j < p.N * 4 * 256; j += 256) s_dep[j] = dep[2 * j];
     __syncthreads();
   }
@@ -77,7 +82,7 @@ __global__ __launch_bounds__(256) void k_linearize(LinParams p, int64_t n,
       atomicMin(bad, (unsigned long long)i);
       c = 0;
     }
-    if (!hi) {
+    if (!wide) {
       const uint64_t* d = s_dep + (size_t)m * 4 * 256;
 #pragma unroll
       for (int k = 0; k < 4; ++k) l |= d[k * 256 + ((c >> (8 * k)) & 255u)];
@@ -93,6 +98,7 @@ __global__ __launch_bounds__(256) void k_linearize(LinParams p, int64_t n,
   }
   lo[i] = l;
   if (hi) hi[i] = h;
+  if (hi32) hi32[i] = (uint32_t)h;
   if (idx) idx[i] = (uint32_t)i;
   }
 }
@@ -105,13 +111,14 @@ __global__ __launch_bounds__(256) void k_gather_u64(const uint64_t* __restrict__
 }
 
 // Keys, values and block keys in sorted order, from the sorted index (slo:
-// bits 0..63, shi: bits 64..127 or NULL): the key gathers every index bit
+// bits 0..63; shi: bits 64..127, or shi32: bits 64..95; or neither): the key gathers every index bit
 // below K into its mode's field through a byte table (enc[k][v]: key bits of
 // byte k holding v); the block key is the index above bit K.
 constexpr int kEncBytes = 8;   // K <= 64
 __global__ __launch_bounds__(256) void k_encode(int64_t n, int K, const uint64_t* __restrict__ enc,
                                                 const uint64_t* __restrict__ slo,
                                                 const uint64_t* __restrict__ shi,
+                                                const uint32_t* __restrict__ shi32,
                                                 const uint32_t* __restrict__ perm,
                                                 const float* __restrict__ vals,
                                                 uint64_t* __restrict__ keys,
@@ -122,7 +129,7 @@ __global__ __launch_bounds__(256) void k_encode(int64_t n, int K, const uint64_t
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const uint64_t l = slo[i], h = shi ? shi[i] : 0;
+  const uint64_t l = slo[i], h = shi ? shi[i] : shi32 ? (uint64_t)shi32[i] : 0;
   const uint64_t low = K >= 64 ? l : (l & ((1ULL << K) - 1));
   uint64_t key = 0;
 #pragma unroll
@@ -341,17 +348,26 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
   StageEvents stage;
   stage.mark(0, s);
   const bool wide = L.T > 64;
+  // an index of 65 to 96 bits is sorted in two parts, its values and high bits moved
+  // through the sort over the low 64 bits, its values and low bits through the sort
+  // over the high ones; a wider one sorts (index, number) pairs and follows the
+  // permutation with gathers; one of at most 64 bits carries the values through its sort
+  const bool mid = wide && L.T <= 96;
+  const bool gathers = wide && !mid;
   uint64_t *lo, *lo2, *hi = nullptr, *hi2 = nullptr, *bkey;
   uint32_t *idx = nullptr, *perm = nullptr, *perm2 = nullptr;
+  uint32_t *h32 = nullptr, *h32s = nullptr, *h32f = nullptr, *vs = nullptr, *tv2 = nullptr;
   unsigned long long* bad;
   if ((rc = pool.get(&lo, nnz)) || (rc = pool.get(&lo2, nnz)) || (rc = pool.get(&bkey, nnz)) ||
       (rc = pool.get(&bad, 1)))
     return rc;
-  // an index over 64 bits is sorted in two parts and needs the permutation; one of
-  // at most 64 bits carries the values through its sort instead
-  if (wide && ((rc = pool.get(&hi, nnz)) || (rc = pool.get(&hi2, nnz)) ||
-               (rc = pool.get(&idx, nnz)) || (rc = pool.get(&perm, nnz)) ||
-               (rc = pool.get(&perm2, nnz))))
+  if (gathers && ((rc = pool.get(&hi, nnz)) || (rc = pool.get(&hi2, nnz)) ||
+                  (rc = pool.get(&idx, nnz)) || (rc = pool.get(&perm, nnz)) ||
+                  (rc = pool.get(&perm2, nnz))))
+    return rc;
+  if (mid && ((rc = pool.get(&h32, nnz)) || (rc = pool.get(&h32s, nnz)) ||
+              (rc = pool.get(&h32f, nnz)) || (rc = pool.get(&vs, nnz)) ||
+              (rc = pool.get(&tv2, nnz))))
     return rc;
   // 1. linearize, through per-byte deposit tables
   std::vector<uint64_t> dep((size_t)L.N * 4 * 256 * 2, 0);
@@ -378,7 +394,7 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
   if (nnz > 0)
     hipLaunchKernelGGL(k_linearize, dim3(std::min<unsigned>(grid_of(nnz), kStrideGrid)), dim3(256),
                        wide ? 0 : (size_t)L.N * 4 * 256 * sizeof(uint64_t), s, lp, nnz, d_dep, lo,
-                       hi, idx, bad);
+                       hi, h32, idx, bad);
   HIPCHK(hipGetLastError());
   unsigned long long first_bad = ~0ULL;
   HIPCHK(hipMemcpyAsync(&first_bad, bad, 8, hipMemcpyDeviceToHost, s));
@@ -409,11 +425,32 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
     if ((rc = pool.get(&tk, nnz)) || (rc = pool.get(&tv, nnz)) ||
         (rc = pool.get(&ws, sort_workspace_words(nnz))))
       return rc;
+    if (mid) {
+      // low 64 bits, moving the values and the high bits; then the high bits, moving
+      // the values (into the tensor) and the low bits
+      SortVals v1 = {};
+      v1.in32[0] = reinterpret_cast<const uint32_t*>(values);
+      v1.in32[1] = h32;
+      v1.out32[0] = vs;
+      v1.out32[1] = h32s;
+      v1.tmp32[0] = tv;
+      v1.tmp32[1] = tv2;
+      if ((rc = radix_sort_u64_vals(lo, lo2, tk, v1, nnz, nb0, ws, s))) return rc;
+      SortVals v2 = {};
+      v2.in32[0] = vs;
+      v2.out32[0] = reinterpret_cast<uint32_t*>(t->d_vals);
+      v2.tmp32[0] = tv2;
+      v2.in64 = lo2;
+      v2.out64 = lo;   // the unsorted low bits are no longer needed
+      v2.tmp64 = tk;
+      if ((rc = radix_sort_u32_vals(h32s, h32f, tv, v2, nnz, L.T - 64, ws, s))) return rc;
+      std::swap(lo, lo2);   // lo2: the low bits in the final order
+    }
     // at most 64 index bits: the values travel with the keys into the tensor
     const uint32_t* payload = wide ? idx : reinterpret_cast<const uint32_t*>(values);
     uint32_t* moved = wide ? perm : reinterpret_cast<uint32_t*>(t->d_vals);
-    if ((rc = radix_sort_u64(lo, payload, lo2, moved, tk, tv, nnz, nb0, ws, s))) return rc;
-    if (wide) {
+    if (!mid && (rc = radix_sort_u64(lo, payload, lo2, moved, tk, tv, nnz, nb0, ws, s))) return rc;
+    if (gathers) {
       // the high bits in that order, a stable sort over them, then the low
       // bits in the final order
       if ((rc = pool.get(&hi_sorted, nnz))) return rc;
@@ -454,7 +491,8 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
   const bool blocked = L.S > 0;
   if (nnz > 0) {
     hipLaunchKernelGGL(k_encode, dim3(grid_of(nnz)), dim3(256), 0, s, nnz, L.K, d_enc, lo2,
-                       hi_sorted, perm, values, t->d_keys, t->d_vals, blocked ? bkey : nullptr);
+                       hi_sorted, mid ? h32f : nullptr, gathers ? perm : nullptr, values,
+                       t->d_keys, t->d_vals, blocked ? bkey : nullptr);
     HIPCHK(hipGetLastError());
   }
   // 4. runs of equal block key

@@ -132,6 +132,22 @@ int radix_sort_u32(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uin
                    uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits, bool descending,
                    unsigned int* ws, void* s);
 
+// The same sort with more values moved along: up to two u32 arrays (in32[0], then
+// in32[1]) and one u64 array, at most three words per key (two u32 arrays exclude the
+// u64 one); each output and spare array holds n entries, unused entries are NULL.
+struct SortVals {
+  const uint32_t* in32[2];
+  uint32_t* out32[2];
+  uint32_t* tmp32[2];
+  const uint64_t* in64;
+  uint64_t* out64;
+  uint64_t* tmp64;
+};
+int radix_sort_u64_vals(const uint64_t* kin, uint64_t* kout, uint64_t* ktmp, const SortVals& v,
+                        int64_t n, int bits, unsigned int* ws, void* s);
+int radix_sort_u32_vals(const uint32_t* kin, uint32_t* kout, uint32_t* ktmp, const SortVals& v,
+                        int64_t n, int bits, unsigned int* ws, void* s);
+
 // The indices i < n with flag[i] != 0, ascending, into out; their number into
 // *count (host).  ws holds select_workspace_words(n) words.
 size_t select_workspace_words(int64_t n);

@@ -2,7 +2,8 @@
 // non-zeros are ordered along the encoding line), written for gfx950.
 //
 // radix_sort: stable least-significant-digit radix sort of keys (u32 or u64)
-// with optional u32 values, over key bits [0, bits), 8-bit digits:
+// with up to two u32 value arrays and one u64 value array moved along, over key
+// bits [0, bits), 8-bit digits:
 //   * one pass over the keys forms their bitwise AND and OR: a pass whose digit
 //     is the same for every key (the two agree on its bits) is skipped;
 //   * per pass, over tiles of kSortTile keys: k_sort_count counts the tile's
@@ -191,7 +192,16 @@ __global__ __launch_bounds__(256) void k_digit_base(const unsigned int* __restri
   dbase[tid] = before;
 }
 
-// One pass: every key (and value) of a tile to its place.  Wave w ranks its
+// The value arrays one scatter pass reads and writes: NV u32 arrays and, with V64,
+// one u64 array.
+struct PassVals {
+  const uint32_t* in[2];
+  uint32_t* out[2];
+  const uint64_t* in64;
+  uint64_t* out64;
+};
+
+// One pass: every key (and its values) of a tile to its place.  Wave w ranks its
 // kWaveKeys keys among themselves, 64 at a time in input order: a key's rank is
 // the wave's earlier keys of the same digit (an LDS counter per wave and digit,
 // read by every lane and advanced by the lowest lane of each digit group) plus
@@ -199,16 +209,17 @@ __global__ __launch_bounds__(256) void k_digit_base(const unsigned int* __restri
 // offset inside each digit, the tile's digit counts their starts, and the tile
 // is staged in LDS in digit order and written out, each digit's keys as one
 // contiguous run starting at the (digit, tile) start from k_sort_scan.
-template <typename K, bool HAS_V, bool DESC>
+template <typename K, int NV, bool V64, bool DESC>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
-    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
-    uint32_t* __restrict__ vout, int64_t n, int shift, int64_t ntiles,
-    const unsigned int* __restrict__ tstart, const unsigned int* __restrict__ dbase) {
+    const K* __restrict__ kin, K* __restrict__ kout, PassVals pv, int64_t n, int shift,
+    int64_t ntiles, const unsigned int* __restrict__ tstart,
+    const unsigned int* __restrict__ dbase) {
   __shared__ unsigned int s_cnt[kSortWaves][kDigits];   // per-wave counts, then wave offsets
   __shared__ unsigned int s_start[kDigits];             // tile's first position per digit
   __shared__ unsigned int s_gpos[kDigits];              // global start per digit
   __shared__ K s_k[kSortTile];
-  __shared__ uint32_t s_v[HAS_V ? kSortTile : 1];
+  __shared__ uint32_t s_v[NV > 0 ? NV : 1][NV > 0 ? kSortTile : 1];
+  __shared__ uint64_t s_v64[V64 ? kSortTile : 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int d = tid; d < kDigits; d += kSortThreads) {
     s_gpos[d] = dbase[d] + tstart[(int64_t)d * ntiles + blockIdx.x];
@@ -219,14 +230,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   const int64_t wb = base + (int64_t)w * kWaveKeys;
   K key[kSortRounds];
-  uint32_t val[kSortRounds];
+  uint32_t val[NV > 0 ? NV : 1][kSortRounds];
+  uint64_t val64[V64 ? kSortRounds : 1];
   uint32_t rank[kSortRounds];   // rank among this wave's keys of the same digit
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {   // every load in flight before the ranking
     const int64_t i = wb + r * 64 + lane;
     const bool ok = i < n;
     key[r] = ok ? kin[i] : K(0);
-    if constexpr (HAS_V) val[r] = ok ? vin[i] : 0u;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) val[j][r] = ok ? pv.in[j][i] : 0u;
+    if constexpr (V64) val64[r] = ok ? pv.in64[i] : 0ull;
   }
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
@@ -283,7 +297,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
       const uint32_t d = digit_of<K, DESC>(key[r], shift);
       const uint32_t p = s_start[d] + s_cnt[w][d] + rank[r];
       s_k[p] = key[r];
-      if constexpr (HAS_V) s_v[p] = val[r];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) s_v[j][p] = val[j][r];
+      if constexpr (V64) s_v64[p] = val64[r];
     }
   }
   __syncthreads();
@@ -294,7 +310,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint32_t d = digit_of<K, DESC>(k, shift);
     const int64_t g = (int64_t)s_gpos[d] + (j - (int)s_start[d]);
     kout[g] = k;
-    if constexpr (HAS_V) vout[g] = s_v[j];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) pv.out[q][g] = s_v[q][j];
+    if constexpr (V64) pv.out64[g] = s_v64[j];
   }
 }
 
@@ -370,12 +388,17 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_write(const uint8_t* __rest
 unsigned grid256(int64_t n) { return (unsigned)std::max<int64_t>((n + 255) / 256, 1); }
 
 template <typename K, bool DESC>
-int sort_impl(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, K* ktmp, uint32_t* vtmp,
-              int64_t n, int bits, unsigned int* ws, hipStream_t s) {
-  const bool has_v = vin != nullptr;
+int sort_impl(const K* kin, K* kout, K* ktmp, const SortVals& v, int64_t n, int bits,
+              unsigned int* ws, hipStream_t s) {
+  const int nv = v.in32[0] ? (v.in32[1] ? 2 : 1) : 0;
+  const bool v64 = v.in64 != nullptr;
   if (n <= 0) return BLCO_OK;
   if (n >= ((int64_t)1 << 31))
     return set_error(BLCO_EUNSUPPORTED, "radix sort of %lld keys (at most 2^31 - 1)", (long long)n);
+  if (v.in32[1] && !v.in32[0])
+    return set_error(BLCO_EINVAL, "radix sort: second u32 value array without a first");
+  if (v64 && nv > 1)
+    return set_error(BLCO_EUNSUPPORTED, "radix sort: two u32 and one u64 value arrays");
   const int npass = std::min(kMaxPasses, (std::max(bits, 1) + 7) / 8);
   const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
   unsigned long long* andor = reinterpret_cast<unsigned long long*>(ws);   // 2 x u64
@@ -394,26 +417,37 @@ int sort_impl(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, K* ktm
   std::vector<int> passes;
   for (int p = 0; p < npass; ++p)
     if (((ao[0] ^ ao[1]) >> (8 * p)) & 255ull) passes.push_back(p);
+  const unsigned cgrid = (unsigned)std::min<int64_t>(grid256(n), 8192);
   if (passes.empty()) {
-    hipLaunchKernelGGL((k_copy<K>), dim3((unsigned)std::min<int64_t>(grid256(n), 8192)), dim3(256),
-                       0, s, kin, kout, n);
+    hipLaunchKernelGGL((k_copy<K>), dim3(cgrid), dim3(256), 0, s, kin, kout, n);
     SORT_HIPCHK(hipGetLastError());
-    if (has_v) {
-      hipLaunchKernelGGL((k_copy<uint32_t>), dim3((unsigned)std::min<int64_t>(grid256(n), 8192)),
-                         dim3(256), 0, s, vin, vout, n);
+    for (int j = 0; j < nv; ++j) {
+      hipLaunchKernelGGL((k_copy<uint32_t>), dim3(cgrid), dim3(256), 0, s, v.in32[j], v.out32[j], n);
+      SORT_HIPCHK(hipGetLastError());
+    }
+    if (v64) {
+      hipLaunchKernelGGL((k_copy<uint64_t>), dim3(cgrid), dim3(256), 0, s, v.in64, v.out64, n);
       SORT_HIPCHK(hipGetLastError());
     }
     return BLCO_OK;
   }
   // the passes alternate between the output and the spare buffers so that the
-  // last one writes the output; the input is only read
+  // last one writes the output; the inputs are only read
   const int P = (int)passes.size();
   for (int q = 0; q < P; ++q) {
     const int p = passes[q];
-    const K* ki = q == 0 ? kin : (((P - q) % 2 == 0) ? kout : ktmp);
-    const uint32_t* vi = q == 0 ? vin : (((P - q) % 2 == 0) ? vout : vtmp);
-    K* ko = ((P - 1 - q) % 2 == 0) ? kout : ktmp;
-    uint32_t* vo = ((P - 1 - q) % 2 == 0) ? vout : vtmp;
+    const bool from_in = q == 0, from_out = ((P - q) % 2 == 0), to_out = ((P - 1 - q) % 2 == 0);
+    const K* ki = from_in ? kin : (from_out ? kout : ktmp);
+    K* ko = to_out ? kout : ktmp;
+    PassVals pv = {};
+    for (int j = 0; j < nv; ++j) {
+      pv.in[j] = from_in ? v.in32[j] : (from_out ? v.out32[j] : v.tmp32[j]);
+      pv.out[j] = to_out ? v.out32[j] : v.tmp32[j];
+    }
+    if (v64) {
+      pv.in64 = from_in ? v.in64 : (from_out ? v.out64 : v.tmp64);
+      pv.out64 = to_out ? v.out64 : v.tmp64;
+    }
     hipLaunchKernelGGL((k_sort_count<K, DESC>), dim3((unsigned)ntiles), dim3(kSortThreads), 0, s,
                        ki, n, 8 * p, ntiles, tc);
     SORT_HIPCHK(hipGetLastError());
@@ -424,15 +458,21 @@ int sort_impl(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, K* ktm
     hipLaunchKernelGGL(k_digit_base, dim3(1), dim3(kDigits), 0, s, (const unsigned int*)tot,
                        dbase);
     SORT_HIPCHK(hipGetLastError());
-    if (has_v)
-      hipLaunchKernelGGL((k_sort_scatter<K, true, DESC>), dim3((unsigned)ntiles),
-                         dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, 8 * p, ntiles,
-                         (const unsigned int*)tc, (const unsigned int*)dbase);
+    const dim3 g((unsigned)ntiles), b(kSortThreads);
+    const unsigned int* ts = tc;
+    const unsigned int* db = dbase;
+    if (v64)
+      hipLaunchKernelGGL((k_sort_scatter<K, 1, true, DESC>), g, b, 0, s, ki, ko, pv, n, 8 * p,
+                         ntiles, ts, db);
+    else if (nv == 2)
+      hipLaunchKernelGGL((k_sort_scatter<K, 2, false, DESC>), g, b, 0, s, ki, ko, pv, n, 8 * p,
+                         ntiles, ts, db);
+    else if (nv == 1)
+      hipLaunchKernelGGL((k_sort_scatter<K, 1, false, DESC>), g, b, 0, s, ki, ko, pv, n, 8 * p,
+                         ntiles, ts, db);
     else
-      hipLaunchKernelGGL((k_sort_scatter<K, false, DESC>), dim3((unsigned)ntiles),
-                         dim3(kSortThreads), 0, s, ki, (const uint32_t*)nullptr, ko,
-                         (uint32_t*)nullptr, n, 8 * p, ntiles, (const unsigned int*)tc,
-                         (const unsigned int*)dbase);
+      hipLaunchKernelGGL((k_sort_scatter<K, 0, false, DESC>), g, b, 0, s, ki, ko, pv, n, 8 * p,
+                         ntiles, ts, db);
     SORT_HIPCHK(hipGetLastError());
   }
   return BLCO_OK;
@@ -445,10 +485,18 @@ size_t sort_workspace_words(int64_t n) {
   return (size_t)4 + 2 * kDigits + (size_t)kDigits * ntiles;
 }
 
+static SortVals one_value(const uint32_t* vin, uint32_t* vout, uint32_t* vtmp) {
+  SortVals v = {};
+  v.in32[0] = vin;
+  v.out32[0] = vout;
+  v.tmp32[0] = vtmp;
+  return v;
+}
+
 int radix_sort_u64(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
                    uint64_t* ktmp, uint32_t* vtmp, int64_t n, int bits, unsigned int* ws,
                    void* s) {
-  return sort_impl<uint64_t, false>(kin, vin, kout, vout, ktmp, vtmp, n, bits, ws,
+  return sort_impl<uint64_t, false>(kin, kout, ktmp, one_value(vin, vout, vtmp), n, bits, ws,
                                     (hipStream_t)s);
 }
 
@@ -456,8 +504,19 @@ int radix_sort_u32(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uin
                    uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits, bool descending,
                    unsigned int* ws, void* sv) {
   hipStream_t s = (hipStream_t)sv;
-  return descending ? sort_impl<uint32_t, true>(kin, vin, kout, vout, ktmp, vtmp, n, bits, ws, s)
-                    : sort_impl<uint32_t, false>(kin, vin, kout, vout, ktmp, vtmp, n, bits, ws, s);
+  const SortVals v = one_value(vin, vout, vtmp);
+  return descending ? sort_impl<uint32_t, true>(kin, kout, ktmp, v, n, bits, ws, s)
+                    : sort_impl<uint32_t, false>(kin, kout, ktmp, v, n, bits, ws, s);
+}
+
+int radix_sort_u64_vals(const uint64_t* kin, uint64_t* kout, uint64_t* ktmp, const SortVals& v,
+                        int64_t n, int bits, unsigned int* ws, void* s) {
+  return sort_impl<uint64_t, false>(kin, kout, ktmp, v, n, bits, ws, (hipStream_t)s);
+}
+
+int radix_sort_u32_vals(const uint32_t* kin, uint32_t* kout, uint32_t* ktmp, const SortVals& v,
+                        int64_t n, int bits, unsigned int* ws, void* s) {
+  return sort_impl<uint32_t, false>(kin, kout, ktmp, v, n, bits, ws, (hipStream_t)s);
 }
 
 size_t select_workspace_words(int64_t n) {

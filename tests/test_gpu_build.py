@@ -74,6 +74,19 @@ def test_index_over_64_bits(key_bits, cap):
     assert t.info()["total_bits"] == 76 and t.info()["nruns"] > 1
 
 
+@pytest.mark.parametrize("dims", [(1 << 24,) * 4, (1 << 24, 1 << 24, 1 << 24, 1 << 25),
+                                  (1 << 25,) * 4])
+def test_index_of_96_bits_and_over(dims):
+    # 96 bits: the two-part sort moves the values and the high 32 bits along; 97 and
+    # 100 bits: the (index, number) sort and the gathers
+    rng = np.random.default_rng(len(dims) + int(np.log2(dims[-1])))
+    nnz = 200_000
+    coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
+    vals = rng.random(nnz).astype(np.float32)
+    t = same(coords, vals, dims, key_bits=64, max_block_nnz=5000)
+    assert t.info()["total_bits"] == sum(int(np.log2(d)) for d in dims)
+
+
 def test_zipf_recipe_frequent_rows_and_mttkrp():
     w = synth.WORKLOADS["zipf3"]
     coords, vals = synth.workload_tensor(w, nnz=3_000_000)
