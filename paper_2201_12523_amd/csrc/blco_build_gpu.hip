@@ -6,15 +6,13 @@
 //      goes to position pos[n][j] of a 64- or 128-bit index (per-byte deposit
 //      tables); out-of-range coordinates are flagged;
 //   2. a stable radix sort along the encoding line (blco_sort.hip), least
-//      significant digits first: one sort over the low 64 bits, then, for
-//      indices over 64 bits, one over the high bits.  Indices of at most 96 bits
-//      move the values and the high bits through the first sort and the values
-//      and the low bits through the second; wider ones sort (index, non-zero
-//      number) pairs and gather the high bits, then the low bits, in each order;
+//      significant digits first, the values moved along: one sort over the low
+//      64 bits, then, for indices over 64 bits, one over the high bits.  The first
+//      also moves the high bits (32-bit words for indices of at most 96 bits), the
+//      second the low bits, so no array follows a permutation by gathers;
 //   3. re-encoding in sorted order (Figure 6b) from the sorted index: every
 //      index bit below K moves to its mode's field (a byte table), the block
-//      key is the index above bit K; the values rode along in the sort, or, for
-//      indices over 96 bits, follow the permutation;
+//      key is the index above bit K;
 //   4. runs of equal block key (flags and a stream compaction), copied to the host, where
 //      the block list, per-run high bits and tile table are finished by the
 //      same code as the host builder;
@@ -54,8 +52,8 @@ struct LinParams {
 };
 
 // ALTO index of every non-zero (lo: bits 0..63; hi: bits 64..127, or hi32: bits
-// 64..95 of an index of at most 96 bits; or neither) and, when idx is given, its
-// number; *bad = smallest non-zero number with a coordinate out of range.
+// 64..95 of an index of at most 96 bits; or neither); *bad = smallest non-zero
+// number with a coordinate out of range.
 // dep[((m * 4 + k) * 256 + v) * 2 + {0, 1}]: the (lo, hi) index bits of byte k of a
 // mode-m coordinate holding v.  Without a high part the lo halves of the table are
 // staged in LDS (N * 8 KiB of dynamic LDS), once per workgroup of a grid that
@@ -65,7 +63,6 @@ __global__ __launch_bounds__(256) void k_linearize(LinParams p, int64_t n,
                                                    uint64_t* __restrict__ lo,
                                                    uint64_t* __restrict__ hi,
                                                    uint32_t* __restrict__ hi32,
-                                                   uint32_t* __restrict__ idx,
                                                    unsigned long long* __restrict__ bad) {
   extern __shared__ uint64_t s_dep[];   // [(m * 4 + k) * 256 + v], lo halves (no high part)
   const bool wide = hi || hi32;
@@ -99,30 +96,20 @@ __global__ __launch_bounds__(256) void k_linearize(LinParams p, int64_t n,
   lo[i] = l;
   if (hi) hi[i] = h;
   if (hi32) hi32[i] = (uint32_t)h;
-  if (idx) idx[i] = (uint32_t)i;
   }
 }
 
-__global__ __launch_bounds__(256) void k_gather_u64(const uint64_t* __restrict__ src,
-                                                    const uint32_t* __restrict__ idx, int64_t n,
-                                                    uint64_t* __restrict__ dst) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) dst[i] = src[idx[i]];
-}
-
-// Keys, values and block keys in sorted order, from the sorted index (slo:
-// bits 0..63; shi: bits 64..127, or shi32: bits 64..95; or neither): the key gathers every index bit
-// below K into its mode's field through a byte table (enc[k][v]: key bits of
-// byte k holding v); the block key is the index above bit K.
+// Keys and block keys in sorted order, from the sorted index (slo: bits 0..63;
+// shi: bits 64..127, or shi32: bits 64..95; or neither): the key gathers every index
+// bit below K into its mode's field through a byte table (enc[k][v]: key bits of
+// byte k holding v); the block key is the index above bit K.  The values are
+// already in place: the sorts moved them.
 constexpr int kEncBytes = 8;   // K <= 64
 __global__ __launch_bounds__(256) void k_encode(int64_t n, int K, const uint64_t* __restrict__ enc,
                                                 const uint64_t* __restrict__ slo,
                                                 const uint64_t* __restrict__ shi,
                                                 const uint32_t* __restrict__ shi32,
-                                                const uint32_t* __restrict__ perm,
-                                                const float* __restrict__ vals,
                                                 uint64_t* __restrict__ keys,
-                                                float* __restrict__ vout,
                                                 uint64_t* __restrict__ bkey) {
   __shared__ uint64_t s_enc[kEncBytes * 256];
   for (int i = threadIdx.x; i < kEncBytes * 256; i += 256) s_enc[i] = enc[i];
@@ -135,7 +122,6 @@ __global__ __launch_bounds__(256) void k_encode(int64_t n, int K, const uint64_t
 #pragma unroll
   for (int k = 0; k < kEncBytes; ++k) key |= s_enc[k * 256 + ((low >> (8 * k)) & 255)];
   keys[i] = key;
-  if (perm) vout[i] = vals[perm[i]];   // else the sort already moved the values
   if (!bkey) return;
   uint64_t B;
   if (K >= 64)
@@ -348,26 +334,24 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
   StageEvents stage;
   stage.mark(0, s);
   const bool wide = L.T > 64;
-  // an index of 65 to 96 bits is sorted in two parts, its values and high bits moved
-  // through the sort over the low 64 bits, its values and low bits through the sort
-  // over the high ones; a wider one sorts (index, number) pairs and follows the
-  // permutation with gathers; one of at most 64 bits carries the values through its sort
+  // an index over 64 bits is sorted in two parts: the sort over the low 64 bits moves
+  // the values and the high bits (32-bit words up to 96 bits, else 64-bit), the sort
+  // over the high bits moves the values and the low bits; one of at most 64 bits
+  // carries the values through its one sort
   const bool mid = wide && L.T <= 96;
-  const bool gathers = wide && !mid;
-  uint64_t *lo, *lo2, *hi = nullptr, *hi2 = nullptr, *bkey;
-  uint32_t *idx = nullptr, *perm = nullptr, *perm2 = nullptr;
+  uint64_t *lo, *lo2, *hi = nullptr, *his = nullptr, *hif = nullptr, *bkey;
   uint32_t *h32 = nullptr, *h32s = nullptr, *h32f = nullptr, *vs = nullptr, *tv2 = nullptr;
   unsigned long long* bad;
   if ((rc = pool.get(&lo, nnz)) || (rc = pool.get(&lo2, nnz)) || (rc = pool.get(&bkey, nnz)) ||
       (rc = pool.get(&bad, 1)))
     return rc;
-  if (gathers && ((rc = pool.get(&hi, nnz)) || (rc = pool.get(&hi2, nnz)) ||
-                  (rc = pool.get(&idx, nnz)) || (rc = pool.get(&perm, nnz)) ||
-                  (rc = pool.get(&perm2, nnz))))
+  if (wide && ((rc = pool.get(&vs, nnz)) || (rc = pool.get(&tv2, nnz))))
     return rc;
   if (mid && ((rc = pool.get(&h32, nnz)) || (rc = pool.get(&h32s, nnz)) ||
-              (rc = pool.get(&h32f, nnz)) || (rc = pool.get(&vs, nnz)) ||
-              (rc = pool.get(&tv2, nnz))))
+              (rc = pool.get(&h32f, nnz))))
+    return rc;
+  if (wide && !mid && ((rc = pool.get(&hi, nnz)) || (rc = pool.get(&his, nnz)) ||
+                       (rc = pool.get(&hif, nnz))))
     return rc;
   // 1. linearize, through per-byte deposit tables
   std::vector<uint64_t> dep((size_t)L.N * 4 * 256 * 2, 0);
@@ -394,7 +378,7 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
   if (nnz > 0)
     hipLaunchKernelGGL(k_linearize, dim3(std::min<unsigned>(grid_of(nnz), kStrideGrid)), dim3(256),
                        wide ? 0 : (size_t)L.N * 4 * 256 * sizeof(uint64_t), s, lp, nnz, d_dep, lo,
-                       hi, h32, idx, bad);
+                       mid ? nullptr : hi, h32, bad);
   HIPCHK(hipGetLastError());
   unsigned long long first_bad = ~0ULL;
   HIPCHK(hipMemcpyAsync(&first_bad, bad, 8, hipMemcpyDeviceToHost, s));
@@ -416,7 +400,6 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
   HIPCHK(hipMalloc((void**)&t->d_keys, sizeof(uint64_t) * std::max<int64_t>(nnz, 1)));
   HIPCHK(hipMalloc((void**)&t->d_vals, sizeof(float) * std::max<int64_t>(nnz, 1)));
   acc += (sizeof(uint64_t) + sizeof(float)) * (size_t)std::max<int64_t>(nnz, 1);
-  uint64_t* hi_sorted = nullptr;
   if (nnz > 0) {
     const int nb0 = std::max(1, std::min(L.T, 64));
     uint64_t* tk;
@@ -425,42 +408,43 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
     if ((rc = pool.get(&tk, nnz)) || (rc = pool.get(&tv, nnz)) ||
         (rc = pool.get(&ws, sort_workspace_words(nnz))))
       return rc;
-    if (mid) {
-      // low 64 bits, moving the values and the high bits; then the high bits, moving
-      // the values (into the tensor) and the low bits
+    const uint32_t* v_in = reinterpret_cast<const uint32_t*>(values);
+    uint32_t* v_out = reinterpret_cast<uint32_t*>(t->d_vals);
+    if (!wide) {
+      // at most 64 index bits: the values travel with the keys into the tensor
+      if ((rc = radix_sort_u64(lo, v_in, lo2, v_out, tk, tv, nnz, nb0, ws, s))) return rc;
+    } else {
+      // the low 64 bits, moving the values and the high bits; then the high bits,
+      // moving the values (into the tensor) and the low bits
+      uint64_t* tk2;
+      if (!mid && (rc = pool.get(&tk2, nnz))) return rc;
       SortVals v1 = {};
-      v1.in32[0] = reinterpret_cast<const uint32_t*>(values);
-      v1.in32[1] = h32;
+      v1.in32[0] = v_in;
       v1.out32[0] = vs;
-      v1.out32[1] = h32s;
       v1.tmp32[0] = tv;
-      v1.tmp32[1] = tv2;
+      if (mid) {
+        v1.in32[1] = h32;
+        v1.out32[1] = h32s;
+        v1.tmp32[1] = tv2;
+      } else {
+        v1.in64 = hi;
+        v1.out64 = his;
+        v1.tmp64 = tk2;
+      }
       if ((rc = radix_sort_u64_vals(lo, lo2, tk, v1, nnz, nb0, ws, s))) return rc;
       SortVals v2 = {};
       v2.in32[0] = vs;
-      v2.out32[0] = reinterpret_cast<uint32_t*>(t->d_vals);
+      v2.out32[0] = v_out;
       v2.tmp32[0] = tv2;
       v2.in64 = lo2;
       v2.out64 = lo;   // the unsorted low bits are no longer needed
       v2.tmp64 = tk;
-      if ((rc = radix_sort_u32_vals(h32s, h32f, tv, v2, nnz, L.T - 64, ws, s))) return rc;
+      if (mid) {
+        if ((rc = radix_sort_u32_vals(h32s, h32f, tv, v2, nnz, L.T - 64, ws, s))) return rc;
+      } else {
+        if ((rc = radix_sort_u64_vals(his, hif, tk2, v2, nnz, L.T - 64, ws, s))) return rc;
+      }
       std::swap(lo, lo2);   // lo2: the low bits in the final order
-    }
-    // at most 64 index bits: the values travel with the keys into the tensor
-    const uint32_t* payload = wide ? idx : reinterpret_cast<const uint32_t*>(values);
-    uint32_t* moved = wide ? perm : reinterpret_cast<uint32_t*>(t->d_vals);
-    if (!mid && (rc = radix_sort_u64(lo, payload, lo2, moved, tk, tv, nnz, nb0, ws, s))) return rc;
-    if (gathers) {
-      // the high bits in that order, a stable sort over them, then the low
-      // bits in the final order
-      if ((rc = pool.get(&hi_sorted, nnz))) return rc;
-      hipLaunchKernelGGL(k_gather_u64, dim3(grid_of(nnz)), dim3(256), 0, s, hi, perm, nnz, hi2);
-      HIPCHK(hipGetLastError());
-      if ((rc = radix_sort_u64(hi2, perm, hi_sorted, perm2, tk, tv, nnz, L.T - 64, ws, s)))
-        return rc;
-      std::swap(perm, perm2);
-      hipLaunchKernelGGL(k_gather_u64, dim3(grid_of(nnz)), dim3(256), 0, s, lo, perm, nnz, lo2);
-      HIPCHK(hipGetLastError());
     }
   }
   // 3. re-encode in sorted order; keys and values go straight into the tensor
@@ -491,8 +475,8 @@ int build_on_device(int nmodes, const uint64_t* dims, int64_t nnz, const uint32_
   const bool blocked = L.S > 0;
   if (nnz > 0) {
     hipLaunchKernelGGL(k_encode, dim3(grid_of(nnz)), dim3(256), 0, s, nnz, L.K, d_enc, lo2,
-                       hi_sorted, mid ? h32f : nullptr, gathers ? perm : nullptr, values,
-                       t->d_keys, t->d_vals, blocked ? bkey : nullptr);
+                       wide && !mid ? hif : nullptr, mid ? h32f : nullptr, t->d_keys,
+                       blocked ? bkey : nullptr);
     HIPCHK(hipGetLastError());
   }
   // 4. runs of equal block key
