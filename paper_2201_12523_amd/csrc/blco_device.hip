@@ -951,10 +951,13 @@ __global__ __launch_bounds__(kShortB, 8) void k_mttkrp_short(KParams p, int64_t 
 // 8 / RPL at a time, issuing every gather of those records before the first
 // use, and reduce the rank sum across the group.  The residual x - xhat is
 // written in BLCO order; the squared residuals are summed in fp64 per
-// workgroup (k_reduce_loss adds the partials in a fixed order).
-template <int RPL, typename FT, int N, bool BIG>
+// workgroup (k_reduce_loss adds the partials in a fixed order).  bf16 factors take
+// the packed rank layout of the MTTKRP kernels (VEC: one 4- or 8-byte gather).
+template <int RPL, typename FT, int N, bool BIG, bool VEC = false>
 __global__ __launch_bounds__(kBlock) void k_loss_tile(KParams p) {
   constexpr int LPN = 16;
+  constexpr bool PACKED = sizeof(FT) == 2 && RPL > 1;
+  static_assert(!VEC || PACKED, "vector gathers are for packed bf16 ranks");
   constexpr int G = 64 / LPN;                  // groups per wave
   constexpr int PPG = 64 / G;                  // records per group
   constexpr int NF = N + 1;
@@ -995,7 +998,7 @@ __global__ __launch_bounds__(kBlock) void k_loss_tile(KParams p) {
     bool ract[RPL];
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
-      const int r = r0 + rl + q * LPN;
+      const int r = PACKED ? r0 + rl * RPL + q : r0 + rl + q * LPN;
       ract[q] = r < R;
       loff[q] = (uint32_t)(ract[q] ? r : 0) * (uint32_t)sizeof(FT);
     }
@@ -1009,11 +1012,22 @@ __global__ __launch_bounds__(kBlock) void k_loss_tile(KParams p) {
 #pragma unroll
         for (int m = 0; m < N; ++m) {
           const uint32_t f = e[m];
-          if constexpr (BIG) {
+          if constexpr (BIG && PACKED) {
+            const FT* rowp = static_cast<const FT*>(p.A[m]) + (size_t)f * R;
+            float t3[RPL];
+            ld_bf16_run_ptr<RPL, VEC>(rowp + loff[0] / sizeof(FT), ract, t3);
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) v[u][q] *= t3[q];
+          } else if constexpr (BIG) {
             const FT* rowp = static_cast<const FT*>(p.A[m]) + (size_t)f * R;
 #pragma unroll
             for (int q = 0; q < RPL; ++q)
               v[u][q] *= ld_factor<FT>(rowp, (size_t)(loff[q] / sizeof(FT)));
+          } else if constexpr (PACKED) {
+            float t3[RPL];
+            ld_bf16_run<RPL, VEC>(rs[m], f + loff[0], t3);
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) v[u][q] *= t3[q];
           } else {
 #pragma unroll
             for (int q = 0; q < RPL; ++q) v[u][q] *= ld_buf<FT>(rs[m], f + loff[q]);
@@ -1326,18 +1340,27 @@ static int device_cus() {
   return cached[dev];
 }
 
-template <int RPL, typename FT, bool BIG>
-static KernelFn pick_loss(int N) {
+template <int RPL, typename FT, bool BIG, bool VEC>
+static KernelFn pick_loss_v(int N) {
   switch (N) {
-    case 1: return k_loss_tile<RPL, FT, 1, BIG>;
-    case 2: return k_loss_tile<RPL, FT, 2, BIG>;
-    case 3: return k_loss_tile<RPL, FT, 3, BIG>;
-    case 4: return k_loss_tile<RPL, FT, 4, BIG>;
-    case 5: return k_loss_tile<RPL, FT, 5, BIG>;
-    case 6: return k_loss_tile<RPL, FT, 6, BIG>;
-    case 7: return k_loss_tile<RPL, FT, 7, BIG>;
-    default: return k_loss_tile<RPL, FT, 8, BIG>;
+    case 1: return k_loss_tile<RPL, FT, 1, BIG, VEC>;
+    case 2: return k_loss_tile<RPL, FT, 2, BIG, VEC>;
+    case 3: return k_loss_tile<RPL, FT, 3, BIG, VEC>;
+    case 4: return k_loss_tile<RPL, FT, 4, BIG, VEC>;
+    case 5: return k_loss_tile<RPL, FT, 5, BIG, VEC>;
+    case 6: return k_loss_tile<RPL, FT, 6, BIG, VEC>;
+    case 7: return k_loss_tile<RPL, FT, 7, BIG, VEC>;
+    default: return k_loss_tile<RPL, FT, 8, BIG, VEC>;
   }
+}
+
+// VEC where the bf16 ranks are packed (two or more per lane) and R is even
+template <int RPL, typename FT, bool BIG>
+static KernelFn pick_loss(int N, int R) {
+  if constexpr (sizeof(FT) == 2 && RPL > 1) {
+    if (R % 2 == 0) return pick_loss_v<RPL, FT, BIG, true>(N);
+  }
+  return pick_loss_v<RPL, FT, BIG, false>(N);
 }
 
 // window kernel shape (lanes per non-zero x ranks per lane), chosen by measurement on
@@ -1359,9 +1382,9 @@ static KernelFn select_win(int N, int R, int fdt, bool big, bool stash) {
 
 template <typename FT, bool BIG>
 static KernelFn select_loss_t(int N, int R) {
-  if (R <= 16) return pick_loss<1, FT, BIG>(N);
-  if (R <= 32) return pick_loss<2, FT, BIG>(N);
-  return pick_loss<4, FT, BIG>(N);
+  if (R <= 16) return pick_loss<1, FT, BIG>(N, R);
+  if (R <= 32) return pick_loss<2, FT, BIG>(N, R);
+  return pick_loss<4, FT, BIG>(N, R);
 }
 
 static KernelFn select_loss(int N, int R, int fdt, bool big) {

@@ -296,15 +296,18 @@ def test_mttkrp_v_scaled(res):
     check_entries(out.cpu().numpy(), -1.5 * M, 1.5 * S, label="mttkrp_v")
 
 
-def test_sampled_loss_and_residual():
+@pytest.mark.parametrize("dtype,R", [("fp32", 32), ("bf16", 32), ("bf16", 33), ("bf16", 64)])
+def test_sampled_loss_and_residual(dtype, R):
     rng = np.random.default_rng(31)
     dims = (60, 50, 40, 7)
     nnz = 5000
     coords = [rng.integers(0, d, size=nnz).astype(np.uint32) for d in dims]
     vals = rng.standard_normal(nnz).astype(np.float32)
     t = blco.build(coords, vals, dims)
-    A = [(rng.standard_normal((d, 32)) * 0.6).astype(np.float32) for d in dims]
-    F = _dev_factors(A)
+    A = [(rng.standard_normal((d, R)) * 0.6).astype(np.float32) for d in dims]
+    F = _dev_factors(A, torch.bfloat16 if dtype == "bf16" else torch.float32)
+    if dtype == "bf16":
+        A = [_bf16_round(a) for a in A]   # the oracle on the factors the kernel reads
     loss, resid = blco.sampled_loss(t, F)
     f, e = oracle.cp_loss(coords, vals, A)
     assert abs(float(loss) - f) <= 1e-6 * f
