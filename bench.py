@@ -448,17 +448,20 @@ def short_kernel_name(R, N, ft="float", big=False):
     return f"k_mttkrp_short<{rpl}, {ft}, {N}, {b(big)}, {b(vec)}>"
 
 
-def big_factors(dims, R, sf, n):
-    """Whether mode n's MTTKRP gathers with 64-bit addresses (another factor of 4 GiB or more,
-    or a row of 2 GiB or more), as the library decides."""
-    return R * sf >= (1 << 31) or any(d * R * sf > 0xFFFFFFFF for m, d in enumerate(dims) if m != n)
+def big_factors(dims, R, sf, n, window=True):
+    """Whether mode n's MTTKRP gathers with 64-bit addresses, as the library decides: a row
+    of 2 GiB or more, or another factor of 4 GiB or more (above 4 GiB for the window
+    kernel's fp32 gathers at 33-64 ranks, which reach exactly 4 GiB with 32-bit offsets)."""
+    lim = (1 << 32) if (window and sf == 4 and 32 < R <= 64) else 0xFFFFFFFF
+    return R * sf >= (1 << 31) or any(d * R * sf > lim for m, d in enumerate(dims) if m != n)
 
 
-def mode_kernel(T, n, R, N, ft, big):
+def mode_kernel(T, n, R, N, ft, dims):
     """The kernel one mode's MTTKRP launches (the library's rule, read back)."""
+    sf = 4 if ft == "float" else 2
     if T.resolution(n, R) == "hierarchical":
-        return short_kernel_name(R, N, ft, big)
-    return win_kernel_name(R, N, ft, big, stash=T.stash_rows(n, R) > 0)
+        return short_kernel_name(R, N, ft, big_factors(dims, R, sf, n, window=False))
+    return win_kernel_name(R, N, ft, big_factors(dims, R, sf, n), stash=T.stash_rows(n, R) > 0)
 
 
 def describe(w, nnz):
@@ -597,7 +600,7 @@ def leg_inmemory(args, torch, blco, synth, w, *, check=True, cpu=False, gpu_buil
                     for n in modes]
             sf = 4 if tag == "fp32" else 2
             ft = "float" if tag == "fp32" else "unsigned short"
-            names = [mode_kernel(T, n, R, N, ft, big_factors(w.dims, R, sf, n)) for n in modes]
+            names = [mode_kernel(T, n, R, N, ft, w.dims) for n in modes]
             compulsory = [12 * nnz + sum(distinct[m] * R * sf for m in modes if m != n) +
                           w.dims[n] * R * 4 for n in modes]
             alt = {}

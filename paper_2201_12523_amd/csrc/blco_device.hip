@@ -215,6 +215,18 @@ __device__ __forceinline__ float ld_buf<uint16_t>(__amdgpu_buffer_rsrc_t r, uint
   return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0) << 16);
 }
 
+// fp32 gathers of the window kernel at four ranks per lane (33-64 ranks): a global load
+// from the factor's base (uniform, in scalar registers) plus the zero-extended 32-bit
+// byte offset.  That reaches all of 4 GiB, so a factor of exactly 4 GiB (2^24 rows of 64
+// ranks) keeps 32-bit offsets, where a buffer descriptor's 32-bit size stops one byte
+// short.  Measured on the 4-mode 200M-non-zero workload at R = 64: 17.5 -> 15.1 ms on the
+// mode that gathers such a factor (it took 64-bit addresses before), 15.7 -> 15.2 ms on
+// its other frequent-row mode; at two ranks per lane the same loads were 5% slower on the
+// frequent-row modes, so R <= 32 keeps buffer loads.
+__device__ __forceinline__ float ld_base(const void* A, uint32_t off) {
+  return *reinterpret_cast<const float*>(static_cast<const char*>(A) + off);
+}
+
 // RPL consecutive bf16 factor elements from byte offset off, widened to fp32: one
 // 4- or 8-byte buffer load when VEC (every run starts 4-byte aligned: R is even), else
 // RPL 2-byte loads.  Element k sits at the lower address, in the low half of its word.
@@ -373,6 +385,8 @@ __global__ __launch_bounds__(kWin, WPT >= 4 ? 4 : BLCO_WIN_OCC) void k_mttkrp_wi
   // loads measured faster than 8- and 16-byte ones
   constexpr bool PACKED = sizeof(FT) == 2 && RPL > 1;
   static_assert(!VEC || PACKED, "vector gathers are for packed bf16 ranks");
+  // fp32 gathers at four ranks per lane: ld_base instead of buffer loads
+  constexpr bool BASE32 = sizeof(FT) == 4 && LPN == 16 && RPL == 4 && !RES && !BIG;
   __shared__ __align__(16) uint32_t s_rec[W * NP];  // records by grouped position
   __shared__ uint64_t s_end[W / 64];
   // the histogram (processing) and the carry partial sums (computing) are never
@@ -607,6 +621,9 @@ __global__ __launch_bounds__(kWin, WPT >= 4 ? 4 : BLCO_WIN_OCC) void k_mttkrp_wi
               ld_bf16_run<RPL, VEC>(rs[j], f + loff[0], t3);
 #pragma unroll
               for (int k = 0; k < RPL; ++k) pr[u][k] *= t3[k];
+            } else if constexpr (BASE32) {
+#pragma unroll
+              for (int k = 0; k < RPL; ++k) pr[u][k] *= ld_base(ap[j], f + loff[k]);
             } else {
 #pragma unroll
               for (int k = 0; k < RPL; ++k) pr[u][k] *= ld_buf<FT>(rs[j], f + loff[k]);
@@ -1536,13 +1553,18 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
   const size_t fsz = factor_elem_bytes(fdt);
   p.rowbytes = (uint32_t)((size_t)rank * fsz);
   // factors below 4 GiB are gathered with 32-bit byte offsets, larger ones
-  // with 64-bit addresses
-  bool big = (size_t)rank * fsz >= (1ULL << 31);
+  // with 64-bit addresses; the window kernel's fp32 gathers at 33-64 ranks
+  // (ld_base) also take a factor of exactly 4 GiB with 32-bit offsets
+  const bool row_big = (size_t)rank * fsz >= (1ULL << 31);
+  size_t other = 0;
   for (int m = 0; m < t->lay.N; ++m) {
     const size_t bytes = (size_t)t->lay.dims[m] * rank * fsz;
     p.abytes[m] = (uint32_t)std::min<size_t>(bytes, 0xFFFFFFFFull);
-    if (m != mode && bytes > 0xFFFFFFFFull) big = true;
+    if (m != mode) other = std::max(other, bytes);
   }
+  const bool big = row_big || other > 0xFFFFFFFFull;
+  const bool base32 = fdt == BLCO_F32 && rank > 32 && rank <= 64 && !resid;
+  const bool big_win = row_big || other > (base32 ? (1ULL << 32) : 0xFFFFFFFFull);
   int sw = 0;
   const int res = resolve(t, mode, rank, &sw);
   if (res < 0) return res;
@@ -1567,11 +1589,11 @@ static int launch_mttkrp(const blco_tensor* t, const uint64_t* keys, const float
   }
   {
     const int N = t->lay.N;
-    KernelFn f = resid ? select_res(N, rank, fdt, true) : select_win(N, rank, fdt, big, true);
+    KernelFn f = resid ? select_res(N, rank, fdt, true) : select_win(N, rank, fdt, big_win, true);
     const int K = stash_rows(t, mode, rank, f);
     p.hot = t->d_hot + (size_t)mode * kHotMax;
     p.nhot = K;
-    if (K == 0) f = resid ? select_res(N, rank, fdt, false) : select_win(N, rank, fdt, big, false);
+    if (K == 0) f = resid ? select_res(N, rank, fdt, false) : select_win(N, rank, fdt, big_win, false);
     const int64_t nwin = (n + (int64_t)kWin * win_wpt(N, rank, K > 0, resid) - 1) /
                          ((int64_t)kWin * win_wpt(N, rank, K > 0, resid));
     const size_t dyn = K > 0 ? (size_t)K * rank * 4 + 2 * (size_t)kHotSlots * 4 : 0;

@@ -119,11 +119,19 @@ def test_stale_counters_are_not_used(bench, tmp_path):
 
 
 def test_big_factor_rule(bench):
-    # 2^24 x 64 fp32 = 4 GiB: the other modes gather it with 64-bit addresses
+    # 2^24 x 64 fp32 = 4 GiB: the window kernel's fp32 gathers at 33-64 ranks reach it with
+    # 32-bit offsets, buffer loads (hierarchical kernel) take 64-bit addresses; one row more
+    # and every kernel does
     dims = (1 << 24, 1 << 22, 1 << 20, 1 << 10)
-    assert [bench.big_factors(dims, 64, 4, n) for n in range(4)] == [False, True, True, True]
+    assert not any(bench.big_factors(dims, 64, 4, n) for n in range(4))
+    assert [bench.big_factors(dims, 64, 4, n, window=False) for n in range(4)] == \
+        [False, True, True, True]
+    past = ((1 << 24) + 1,) + dims[1:]
+    assert [bench.big_factors(past, 64, 4, n) for n in range(4)] == [False, True, True, True]
     assert not any(bench.big_factors(dims, 32, 4, n) for n in range(4))
     assert not any(bench.big_factors(dims, 64, 2, n) for n in range(4))
+    # bf16 at 128 ranks: 4 GiB through packed buffer loads, which stop one byte short
+    assert [bench.big_factors(dims, 128, 2, n) for n in range(4)] == [False, True, True, True]
 
 
 def test_request_model(bench, tmp_path):

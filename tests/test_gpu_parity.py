@@ -172,14 +172,17 @@ def test_window_boundaries(nnz, R, N):
              resolutions=("register", "frequent"))
 
 
-@pytest.mark.parametrize("dtype,R", [("fp32", 64), ("bf16", 64), ("bf16", 34)])
-def test_register_path_factor_past_4gib(dtype, R):
+@pytest.mark.parametrize("dtype,R,exact", [("fp32", 64, False), ("bf16", 64, False),
+                                           ("bf16", 34, False), ("fp32", 64, True)])
+def test_register_path_factor_past_4gib(dtype, R, exact):
     """Register-based MTTKRP of the two short modes when the long mode's factor is just
     past 4 GiB, so the kernel gathers through 64-bit addresses instead of 32-bit buffer
-    offsets, with and without the frequent-row stash (packed bf16 ranks at R = 34)."""
+    offsets, with and without the frequent-row stash (packed bf16 ranks at R = 34); and
+    (exact) a factor of exactly 4 GiB at 64 fp32 ranks, which the kernel still reaches with
+    32-bit offsets from the factor's base, its last row included."""
     fsz = 4 if dtype == "fp32" else 2
-    rows0 = max(1 << 24, (1 << 32) // (R * fsz) + 1)
-    assert rows0 * R * fsz > 0xFFFFFFFF
+    rows0 = (1 << 32) // (R * fsz) if exact else max(1 << 24, (1 << 32) // (R * fsz) + 1)
+    assert rows0 * R * fsz == 1 << 32 if exact else rows0 * R * fsz > 0xFFFFFFFF
     rng = np.random.default_rng(R + fsz)
     dims = (rows0, 100, 60)
     nnz = 300_000
